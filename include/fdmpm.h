@@ -1,0 +1,178 @@
+/*
+ * fdmpm.h -- C ABI of the MI355X (gfx950) particle-mesh step for fuzzy dark
+ * matter (Veltmaat & Niemeyer, arXiv:1608.00802).
+ *
+ * One step of the method: cloud-in-cell mass deposit of the particles on a
+ * periodic mesh, FFT Poisson solve for the gravitational potential, the
+ * quantum pressure Q = -(hbar^2/2m^2) lap(sqrt rho)/sqrt rho on the same mesh
+ * (Sec. II A, Eq. (5); comoving form Sec. III, Eq. (18)), central-difference
+ * gradients of both, CIC interpolation back to the particles, and a
+ * kick-drift-kick leapfrog (static box, or comoving in canonical momentum).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Units.  Particle coordinates and the mesh use CELL units: positions
+ *   u in [0, N), the mesh spacing is 1.  Time is the caller's time unit
+ *   (static box) or 1/H0 (comoving box).  Velocities are du/dt in cells per
+ *   time unit (static) or canonical momentum p = a^2 du/dt in cells*H0
+ *   (comoving).  Densities are in units of the mean.  ``box`` converts the
+ *   caller's hbar/m (length^2/time) into cells^2/time.
+ * Layout.  Meshes are C-order [ix][iy][iz] (iz fastest), N^3 contiguous
+ *   float.  Particles are structure-of-arrays: positions [3][Np] (x block,
+ *   then y block, then z block) and velocities / accelerations [3][Np] float.
+ *   Fixed-point positions (PM_FIXED32) store u * 2^32 / N as uint32, so the
+ *   periodic wrap is the natural wrap of 32-bit arithmetic; PM_FP32 positions
+ *   store u as float in [0, N).
+ * Memory ownership.  The caller owns every device buffer: the workspace
+ *   passed to pm_init (size from pm_workspace_bytes, 256-byte aligned) and all
+ *   particle and mesh arrays.  The library never allocates device memory;
+ *   pm_destroy frees only the host-side context.
+ * Workspace contents.  Bytes [0, 8 N^3) of the workspace hold the deposited
+ *   mass mesh after pm_deposit, pm_step or pm_energy: int64 in units of 2^-40
+ *   particle masses (PM_FIXED32; exactly 2^40 per particle in total) or float
+ *   sums of CIC weights (PM_FP32, first 4 N^3 bytes).  Everything else in the
+ *   workspace is private.
+ * Asynchrony.  All calls except pm_workspace_bytes, pm_energy and pm_destroy
+ *   only enqueue work on the context's HIP stream and return.  Argument errors
+ *   are reported synchronously; a kernel launch error is reported as
+ *   PM_EDEVICE.  A context is bound to one stream and is not thread-safe;
+ *   distinct contexts on distinct workspaces are independent.
+ * Devices.  All device pointers must belong to the device that was current
+ *   when pm_init was called; calls must be made with that device current.
+ */
+#ifndef FDMPM_H
+#define FDMPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PM_OK = 0,
+  PM_EINVAL = -1,        /* bad argument: null pointer, out-of-range value */
+  PM_ENOMEM = -2,        /* workspace smaller than pm_workspace_bytes */
+  PM_EDEVICE = -3,       /* a HIP runtime call or kernel launch failed */
+  PM_EUNSUPPORTED = -4,  /* mesh size not a power of two in [16, 512] */
+  PM_ESTATE = -5         /* call needs state that is not there yet */
+} pm_status;
+
+typedef enum {
+  PM_FP32 = 0,     /* float positions, float atomics, direct sqrt(rho) for Q */
+  PM_FIXED32 = 1   /* uint32 fixed-point positions, exact integer deposit,
+                      FP32 FFT/stencils, FP64 for near-empty cells */
+} pm_precision;
+
+/* Problem definition (Sec. II A static box; Sec. III comoving box). */
+typedef struct {
+  int32_t n_mesh;            /* N: cells per side, power of two, 16..512 */
+  int32_t precision;         /* pm_precision */
+  int64_t n_part;            /* particle count (equal masses), >= 1; PM_FIXED32
+                                needs n_part <= 8 N^3 (a cell then holds up to
+                                2^20 times the mean mass) */
+  double box;                /* side length L in the caller's length unit */
+  int32_t comoving;          /* 0: static box (a == 1); 1: flat comoving box */
+  int32_t reserved0;         /* must be 0 */
+  double four_pi_G_rhobar;   /* static box: 4 pi G rho_bar (1/time^2) */
+  double omega_m;            /* comoving: matter density parameter */
+  double omega_l;            /* comoving: cosmological constant */
+  double h0;                 /* comoving: H0 in 1/time (use 1 for time in 1/H0) */
+  double hbar_over_m;        /* hbar/m in length^2/time; 0 disables quantum pressure */
+  double rho_floor;          /* floor on rho/rho_bar inside Q, > 0 (1e-6 typical) */
+  double rho_fp64_below;     /* PM_FIXED32: cells with rho/rho_bar below this
+                                compute sqrt(rho) and Q in FP64 from the exact
+                                integer mass; 0 disables (1e-3 typical) */
+} pm_params;
+
+/* Energies in cell units with the mean density as mass unit (mass per cell
+ * 1, per particle N^3/Np):
+ *   K = sum_p (N^3/Np) |p|^2 / (2 a^2)                    (Eq. (8))
+ *   W = 1/(2a) sum_j delta_j phi_j                        (potential energy)
+ *   U = (hbar/m)^2/(2 a^2) sum_j sum_d (s_{j+e_d} - s_j)^2, s = sqrt(max(rho, floor))
+ *       (gradient energy K_rho of Eq. (6), forward differences)
+ *   E = K + W + U.  Multiply by rho_bar dx^5/time^2 for physical units. */
+typedef struct {
+  double K, W, U, E;
+} pm_energies;
+
+typedef struct pm_ctx pm_ctx;
+
+/* Flags of pm_step. */
+#define PM_CONTINUE 1  /* phi and Q held by the context are those of the
+                          positions passed in (left by the previous pm_step
+                          on this context, with unchanged positions): skip
+                          the opening force evaluation */
+
+/* Bytes of device workspace a context with these parameters needs.  Pure
+ * host function, no device access.  Returns PM_EINVAL / PM_EUNSUPPORTED for
+ * parameters pm_init would reject. */
+pm_status pm_workspace_bytes(const pm_params* params, size_t* bytes);
+
+/* Create a context.  d_workspace: device buffer of at least
+ * pm_workspace_bytes bytes, 256-byte aligned, owned by the caller and used
+ * exclusively by this context until pm_destroy.  hip_stream: a hipStream_t
+ * (NULL = default stream).  Enqueues the upload of small constant tables.
+ * *out receives the context on PM_OK and is untouched otherwise. */
+pm_status pm_init(const pm_params* params, void* d_workspace, size_t bytes,
+                  void* hip_stream, pm_ctx** out);
+
+/* Step (i) of Sec. II A with the cloud-in-cell kernel: deposit the particles
+ * at d_pos (uint32 or float [3][Np] per the precision) into the context's
+ * mass mesh and form delta = rho/rho_bar - 1 in the context.  If d_delta is
+ * not NULL, delta (float [N^3]) is also written there. */
+pm_status pm_deposit(pm_ctx* ctx, const void* d_pos, float* d_delta);
+
+/* Gravity: phi with lap(phi) = S delta, S = four_pi_G_rhobar (static) or
+ * 1.5 omega_m h0^2 (comoving, the a-independent potential phi_c), through
+ * the FFT with the Green's function of the 7-point Laplacian, zero mean.
+ * d_delta NULL uses the context's delta from pm_deposit.  The result stays
+ * in the context (for pm_force and pm_step) and is also written to d_phi
+ * (float [N^3]) if not NULL. */
+pm_status pm_poisson(pm_ctx* ctx, const float* d_delta, float* d_phi);
+
+/* Step (ii) of Sec. II A: Q_c = -(hbar/m)^2/2 L7[sqrt R]/sqrt R with
+ * R = max(rho, rho_floor) and L7 the 7-point stencil, in cells^2/time^2
+ * (the comoving Q of Eq. (18) is Q_c / a^2).  d_delta NULL uses the
+ * context's delta and enables the FP64 path for near-empty cells; an
+ * explicit d_delta is used as given (FP32 path only).  The result stays in
+ * the context and is also written to d_q (float [N^3]) if not NULL. */
+pm_status pm_qpot(pm_ctx* ctx, const float* d_delta, float* d_q);
+
+/* Step (iii) in mesh-gradient form: acceleration at the particles,
+ * acc = -grad(phi)/a - grad(Q)/a^2 (a = 1 in a static box), central
+ * differences on the mesh and CIC interpolation with the deposit's weights.
+ * d_phi / d_q NULL use the context's fields.  d_acc: float [3][Np]. */
+pm_status pm_force(pm_ctx* ctx, const float* d_phi, const float* d_q,
+                   const void* d_pos, float* d_acc, double a);
+
+/* Kick-drift-kick leapfrog over the schedule times[0..nsteps] (host array:
+ * times in a static box, scale factors in a comoving box, strictly
+ * increasing).  Positions and velocities are synchronised on entry and on
+ * return; kicks between steps are merged, so each step costs one deposit,
+ * one Poisson solve, one Q evaluation and one fused gather-kick-drift.
+ * Comoving kick factors int da/(a^2 H) (gravity) and int da/(a^3 H) (Q,
+ * drift) are computed on the host in FP64; half-kicks split at sqrt(a0 a1).
+ * flags: PM_CONTINUE or 0.  On return the context's phi and Q are those of
+ * the final positions. */
+pm_status pm_step(pm_ctx* ctx, void* d_pos, float* d_vel, const double* times,
+                  int32_t nsteps, int32_t flags);
+
+/* K, W, U, E of the synchronised state (d_pos, d_vel) at scale factor a
+ * (1 in a static box).  Recomputes delta and phi; blocks until done.
+ * Leaves the context's delta, phi and Q at d_pos. */
+pm_status pm_energy(pm_ctx* ctx, const void* d_pos, const float* d_vel,
+                    double a, pm_energies* out);
+
+/* Free the host-side context (no device memory is owned). */
+pm_status pm_destroy(pm_ctx* ctx);
+
+/* Static, NUL-terminated description of a status code. */
+const char* pm_strerror(pm_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDMPM_H */

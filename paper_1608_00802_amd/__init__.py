@@ -1,0 +1,26 @@
+"""MI355X-native particle-mesh step for fuzzy dark matter (arXiv:1608.00802).
+
+The compute path is the HIP library libfdmpm.so (C ABI in include/fdmpm.h);
+this package holds its ctypes binding, the build script and the serving loop.
+"""
+
+from ._lib import (  # noqa: F401
+    EXPORTED,
+    PM_CONTINUE,
+    PM_FIXED32,
+    PM_FP32,
+    PMContext,
+    PMError,
+    PMParams,
+    load_library,
+    make_params,
+    pm_deposit,
+    pm_destroy,
+    pm_energy,
+    pm_force,
+    pm_init,
+    pm_poisson,
+    pm_qpot,
+    pm_step,
+    pm_workspace_bytes,
+)

@@ -1,0 +1,248 @@
+"""ctypes binding of libfdmpm (C ABI in include/fdmpm.h).
+
+Argument marshalling and host-side validation only: every step of the
+particle-mesh path runs in the HIP kernels of the shared library.  PyTorch
+supplies device memory and the stream.  If the library has not been built
+the import of this module fails loudly; there is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from ctypes import POINTER, byref, c_double, c_int32, c_int64, c_size_t, c_void_p
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfdmpm.so")
+
+PM_OK, PM_EINVAL, PM_ENOMEM, PM_EDEVICE, PM_EUNSUPPORTED, PM_ESTATE = 0, -1, -2, -3, -4, -5
+PM_FP32, PM_FIXED32 = 0, 1
+PM_CONTINUE = 1
+
+EXPORTED = ("pm_workspace_bytes", "pm_init", "pm_deposit", "pm_poisson", "pm_qpot",
+            "pm_force", "pm_step", "pm_energy", "pm_destroy", "pm_strerror")
+
+
+class PMParams(ctypes.Structure):
+    _fields_ = [
+        ("n_mesh", c_int32),
+        ("precision", c_int32),
+        ("n_part", c_int64),
+        ("box", c_double),
+        ("comoving", c_int32),
+        ("reserved0", c_int32),
+        ("four_pi_G_rhobar", c_double),
+        ("omega_m", c_double),
+        ("omega_l", c_double),
+        ("h0", c_double),
+        ("hbar_over_m", c_double),
+        ("rho_floor", c_double),
+        ("rho_fp64_below", c_double),
+    ]
+
+
+class PMEnergies(ctypes.Structure):
+    _fields_ = [("K", c_double), ("W", c_double), ("U", c_double), ("E", c_double)]
+
+
+class PMError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {strerror(status)} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libfdmpm.so once; raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built: call __graft_entry__.build() or "
+                          "python -m paper_1608_00802_amd.build")
+    lib = ctypes.CDLL(path)
+    P = POINTER
+    sig = {
+        "pm_workspace_bytes": ([P(PMParams), P(c_size_t)], c_int32),
+        "pm_init": ([P(PMParams), c_void_p, c_size_t, c_void_p, P(c_void_p)], c_int32),
+        "pm_deposit": ([c_void_p, c_void_p, c_void_p], c_int32),
+        "pm_poisson": ([c_void_p, c_void_p, c_void_p], c_int32),
+        "pm_qpot": ([c_void_p, c_void_p, c_void_p], c_int32),
+        "pm_force": ([c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double], c_int32),
+        "pm_step": ([c_void_p, c_void_p, c_void_p, P(c_double), c_int32, c_int32], c_int32),
+        "pm_energy": ([c_void_p, c_void_p, c_void_p, c_double, P(PMEnergies)], c_int32),
+        "pm_destroy": ([c_void_p], c_int32),
+        "pm_strerror": ([c_int32], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def strerror(status: int) -> str:
+    try:
+        return load_library().pm_strerror(status).decode()
+    except ImportError:
+        return f"status {status}"
+
+
+def _check(status: int, where: str) -> None:
+    if status != PM_OK:
+        raise PMError(status, where)
+
+
+def make_params(n_mesh: int, n_part: int, box: float, *, precision: int = PM_FIXED32,
+                comoving: bool = False, four_pi_G_rhobar: float = 1.0, omega_m: float = 0.3,
+                omega_l: float = 0.7, h0: float = 1.0, hbar_over_m: float = 0.0,
+                rho_floor: float = 1e-6, rho_fp64_below: float = 1e-3) -> PMParams:
+    return PMParams(int(n_mesh), int(precision), int(n_part), float(box), int(bool(comoving)), 0,
+                    float(four_pi_G_rhobar), float(omega_m), float(omega_l), float(h0),
+                    float(hbar_over_m), float(rho_floor), float(rho_fp64_below))
+
+
+# ------------------------------------------------------------------ same-named C calls
+
+def pm_workspace_bytes(params: PMParams) -> int:
+    n = c_size_t(0)
+    _check(load_library().pm_workspace_bytes(byref(params), byref(n)), "pm_workspace_bytes")
+    return n.value
+
+
+def pm_init(params: PMParams, workspace_ptr: int, nbytes: int, stream_ptr: int) -> int:
+    ctx = c_void_p(None)
+    _check(load_library().pm_init(byref(params), c_void_p(workspace_ptr), nbytes,
+                                  c_void_p(stream_ptr), byref(ctx)), "pm_init")
+    return ctx.value
+
+
+def pm_deposit(ctx: int, pos_ptr: int, delta_ptr: int | None) -> None:
+    _check(load_library().pm_deposit(c_void_p(ctx), c_void_p(pos_ptr), c_void_p(delta_ptr)),
+           "pm_deposit")
+
+
+def pm_poisson(ctx: int, delta_ptr: int | None, phi_ptr: int | None) -> None:
+    _check(load_library().pm_poisson(c_void_p(ctx), c_void_p(delta_ptr), c_void_p(phi_ptr)),
+           "pm_poisson")
+
+
+def pm_qpot(ctx: int, delta_ptr: int | None, q_ptr: int | None) -> None:
+    _check(load_library().pm_qpot(c_void_p(ctx), c_void_p(delta_ptr), c_void_p(q_ptr)),
+           "pm_qpot")
+
+
+def pm_force(ctx: int, phi_ptr: int | None, q_ptr: int | None, pos_ptr: int, acc_ptr: int,
+             a: float) -> None:
+    _check(load_library().pm_force(c_void_p(ctx), c_void_p(phi_ptr), c_void_p(q_ptr),
+                                   c_void_p(pos_ptr), c_void_p(acc_ptr), float(a)), "pm_force")
+
+
+def pm_step(ctx: int, pos_ptr: int, vel_ptr: int, times, flags: int = 0) -> None:
+    t = [float(v) for v in times]
+    arr = (c_double * len(t))(*t)
+    _check(load_library().pm_step(c_void_p(ctx), c_void_p(pos_ptr), c_void_p(vel_ptr), arr,
+                                  len(t) - 1, int(flags)), "pm_step")
+
+
+def pm_energy(ctx: int, pos_ptr: int, vel_ptr: int, a: float) -> dict:
+    out = PMEnergies()
+    _check(load_library().pm_energy(c_void_p(ctx), c_void_p(pos_ptr), c_void_p(vel_ptr),
+                                    float(a), byref(out)), "pm_energy")
+    return {"K": out.K, "W": out.W, "U": out.U, "E": out.E}
+
+
+def pm_destroy(ctx: int) -> None:
+    _check(load_library().pm_destroy(c_void_p(ctx)), "pm_destroy")
+
+
+# ------------------------------------------------------------------ torch-facing wrapper
+
+class PMContext:
+    """One particle-mesh problem bound to a torch device and stream.
+
+    The workspace is a torch uint8 tensor owned by this object.  Particle
+    arrays are torch tensors: positions [3, Np] uint32 (fixed point, stored
+    as int32 bit patterns) or float32 (cells), velocities [3, Np] float32.
+    Shapes, dtypes, devices and contiguity are checked here before any call.
+    """
+
+    def __init__(self, params: PMParams, device=None, stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device if device is not None else "cuda:0")
+        if self.device.type != "cuda":
+            raise ValueError("PMContext needs a GPU device")
+        self.params = params
+        self.n = params.n_mesh
+        self.np = params.n_part
+        self.fixed = params.precision == PM_FIXED32
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.nbytes = pm_workspace_bytes(params)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+            self.ctx = pm_init(params, self.workspace.data_ptr(), self.nbytes,
+                               self.stream.cuda_stream)
+
+    # -- validation
+    def _mesh(self, t, name):
+        torch = self.torch
+        if t is None:
+            return None
+        if t.dtype != torch.float32 or t.device != self.device or not t.is_contiguous() \
+                or t.numel() != self.n ** 3:
+            raise ValueError(f"{name}: need contiguous float32 [{self.n}]^3 on {self.device}")
+        return t.data_ptr()
+
+    def _pos(self, t):
+        torch = self.torch
+        want = torch.int32 if self.fixed else torch.float32
+        if t.dtype not in ((torch.int32, torch.uint32) if self.fixed else (torch.float32,)) \
+                or t.device != self.device or not t.is_contiguous() \
+                or tuple(t.shape) != (3, self.np):
+            raise ValueError(f"positions: need contiguous {want} [3, {self.np}] on {self.device}")
+        return t.data_ptr()
+
+    def _vec(self, t, name):
+        torch = self.torch
+        if t.dtype != torch.float32 or t.device != self.device or not t.is_contiguous() \
+                or tuple(t.shape) != (3, self.np):
+            raise ValueError(f"{name}: need contiguous float32 [3, {self.np}] on {self.device}")
+        return t.data_ptr()
+
+    # -- calls
+    def deposit(self, pos, delta_out=None):
+        pm_deposit(self.ctx, self._pos(pos), self._mesh(delta_out, "delta_out"))
+
+    def poisson(self, delta=None, phi_out=None):
+        pm_poisson(self.ctx, self._mesh(delta, "delta"), self._mesh(phi_out, "phi_out"))
+
+    def qpot(self, delta=None, q_out=None):
+        pm_qpot(self.ctx, self._mesh(delta, "delta"), self._mesh(q_out, "q_out"))
+
+    def force(self, pos, acc_out, a=1.0, phi=None, q=None):
+        pm_force(self.ctx, self._mesh(phi, "phi"), self._mesh(q, "q"), self._pos(pos),
+                 self._vec(acc_out, "acc_out"), a)
+
+    def step(self, pos, vel, times, flags=0):
+        if len(times) < 2 or any(not math.isfinite(float(t)) for t in times):
+            raise ValueError("times: need at least two finite values")
+        pm_step(self.ctx, self._pos(pos), self._vec(vel, "vel"), times, flags)
+
+    def energy(self, pos, vel, a=1.0):
+        return pm_energy(self.ctx, self._pos(pos), self._vec(vel, "vel"), a)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            pm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,454 @@
+// Host side of libfdmpm: parameter checks, workspace carving, FP64 time-step
+// factors and the launch sequence of one particle-mesh step.  Implements the
+// C ABI declared in include/fdmpm.h.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "../../include/fdmpm.h"
+#include "internal.h"
+
+using namespace fdm;
+
+struct pm_ctx {
+  pm_params p;
+  int N, logn, B;
+  int64_t np;
+  size_t ncell;
+  hipStream_t stream;
+  bool fixed;
+  bool has_q;
+  // constants in cell units
+  double S;          // static: 4 pi G rho_bar; comoving: 1.5 Om H0^2
+  double hm;         // hbar/m in cells^2/time
+  DeltaConv conv;
+  QConst qc;
+  // workspace
+  void* mass;        // int64 [N^3] (fixed) or float [N^3] accumulator (fp32)
+  float* delta;
+  float* phi;
+  float* q;
+  float2* spec;
+  float2* tw;
+  float* s2;
+  double* partials;  // energy partial sums
+  double* result;    // reduced energies (device)
+  int q_blocks;
+  int k_blocks;
+  bool have_delta;   // delta in the workspace was made by pm_deposit
+  bool have_phi;
+  bool have_q;
+  bool fields_at_pos;  // phi, q correspond to the positions left by pm_step
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+int ilog2_exact(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return (1 << l) == n ? l : -1;
+}
+
+struct Layout {
+  size_t mass, delta, phi, q, spec, tw, s2, partials, result, total;
+};
+
+Layout layout_for(const pm_params& p) {
+  const size_t n = (size_t)p.n_mesh;
+  const size_t nc = n * n * n;
+  Layout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  L.mass = take(8 * nc);
+  L.delta = take(4 * nc);
+  L.phi = take(4 * nc);
+  L.q = take(4 * nc);
+  L.spec = take(8 * (n / 2 + 1) * n * n);
+  L.tw = take(8 * n);
+  L.s2 = take(4 * n);
+  const size_t qb = nc / kBlock;
+  L.partials = take(8 * (2 * qb + 1024));
+  L.result = take(8 * 16);
+  L.total = off;
+  return L;
+}
+
+pm_status check_params(const pm_params* p) {
+  if (!p) return PM_EINVAL;
+  const int logn = ilog2_exact(p->n_mesh);
+  if (logn < 4 || logn > 9) return PM_EUNSUPPORTED;
+  if (p->precision != PM_FP32 && p->precision != PM_FIXED32) return PM_EINVAL;
+  if (p->n_part < 1) return PM_EINVAL;
+  if (!(p->box > 0.0) || !isfinite(p->box)) return PM_EINVAL;
+  if (p->comoving != 0 && p->comoving != 1) return PM_EINVAL;
+  if (p->reserved0 != 0) return PM_EINVAL;
+  if (!(p->hbar_over_m >= 0.0) || !isfinite(p->hbar_over_m)) return PM_EINVAL;
+  if (!(p->rho_floor > 0.0) || !isfinite(p->rho_floor)) return PM_EINVAL;
+  if (!(p->rho_fp64_below >= 0.0) || !isfinite(p->rho_fp64_below)) return PM_EINVAL;
+  if (p->comoving) {
+    if (!(p->omega_m > 0.0) || !(p->omega_l >= 0.0) || !(p->h0 > 0.0)) return PM_EINVAL;
+    if (!isfinite(p->omega_m) || !isfinite(p->omega_l) || !isfinite(p->h0)) return PM_EINVAL;
+  } else {
+    if (!(p->four_pi_G_rhobar >= 0.0) || !isfinite(p->four_pi_G_rhobar)) return PM_EINVAL;
+  }
+  if (p->precision == PM_FIXED32) {
+    // mean integer mass per cell must be an integer: 2^40 Np / N^3
+    if (3 * logn > kMassShift) return PM_EUNSUPPORTED;
+    // a cell can hold at least 2^20 times the mean mass without overflow:
+    // mean = 2^40 Np / N^3 <= 2^43
+    if ((double)p->n_part > 8.0 * (double)p->n_mesh * p->n_mesh * p->n_mesh) return PM_EINVAL;
+  }
+  return PM_OK;
+}
+
+pm_status dev(hipError_t e) { return e == hipSuccess ? PM_OK : PM_EDEVICE; }
+
+#define PM_TRY(expr)                   \
+  do {                                 \
+    pm_status st_ = (expr);            \
+    if (st_ != PM_OK) return st_;      \
+  } while (0)
+
+// ------------------------------------------------------------ FP64 quadrature
+// Gauss-Legendre nodes/weights on [-1, 1] by Newton iteration on P_n.
+struct Gauss {
+  static constexpr int n = 16;
+  double x[n], w[n];
+  Gauss() {
+    for (int i = 0; i < n; ++i) {
+      double z = cos(M_PI * (i + 0.75) / (n + 0.5));
+      double pp = 0.0;
+      for (int it = 0; it < 100; ++it) {
+        double p1 = 1.0, p2 = 0.0;
+        for (int j = 1; j <= n; ++j) {
+          const double p3 = p2;
+          p2 = p1;
+          p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+        }
+        pp = n * (z * p1 - p2) / (z * z - 1.0);
+        const double dz = p1 / pp;
+        z -= dz;
+        if (fabs(dz) < 1e-16) break;
+      }
+      x[i] = z;
+      w[i] = 2.0 / ((1.0 - z * z) * pp * pp);
+    }
+  }
+};
+
+const Gauss& gauss() {
+  static const Gauss g;
+  return g;
+}
+
+double hubble(const pm_params& p, double a) {
+  return p.h0 * sqrt(p.omega_m / (a * a * a) + p.omega_l);
+}
+
+// int_{a0}^{a1} da / (a^pw H(a)), composite Gauss-Legendre in s = ln a
+double a_integral(const pm_params& p, double a0, double a1, int pw) {
+  const Gauss& g = gauss();
+  const double s0 = log(a0), s1 = log(a1);
+  int m = (int)ceil(fabs(s1 - s0) / 0.02);
+  if (m < 1) m = 1;
+  const double hseg = (s1 - s0) / m;
+  double total = 0.0;
+  for (int k = 0; k < m; ++k) {
+    const double c = s0 + (k + 0.5) * hseg;
+    double part = 0.0;
+    for (int i = 0; i < Gauss::n; ++i) {
+      const double s = c + 0.5 * hseg * g.x[i];
+      const double a = exp(s);
+      part += g.w[i] * a / (pow(a, pw) * hubble(p, a));  // da = a ds
+    }
+    total += 0.5 * hseg * part;
+  }
+  return total;
+}
+
+struct Kick {
+  double g, q;
+};
+
+Kick kick(const pm_params& p, double t0, double t1) {
+  if (!p.comoving) return {t1 - t0, t1 - t0};
+  return {a_integral(p, t0, t1, 2), a_integral(p, t0, t1, 3)};
+}
+
+double drift(const pm_params& p, double t0, double t1) {
+  if (!p.comoving) return t1 - t0;
+  return a_integral(p, t0, t1, 3);
+}
+
+double midpoint(const pm_params& p, double t0, double t1) {
+  return p.comoving ? sqrt(t0 * t1) : 0.5 * (t0 + t1);
+}
+
+// ------------------------------------------------------------ launch sequences
+pm_status run_deposit(pm_ctx* c, const void* pos) {
+  PM_TRY(dev(launch_fill_zero(c->mass, 8 * c->ncell, c->stream)));
+  if (c->fixed)
+    return dev(launch_deposit_fixed(static_cast<const uint32_t*>(pos), c->np, c->logn,
+                                    static_cast<unsigned long long*>(c->mass), c->stream));
+  return dev(launch_deposit_f32(static_cast<const float*>(pos), c->np, c->logn,
+                                static_cast<float*>(c->mass), c->stream));
+}
+
+// Forward z-pass from the context's mass mesh (or from a given delta),
+// remaining passes, potential into c->phi.
+pm_status run_poisson(pm_ctx* c, int src, const void* in) {
+  PM_TRY(dev(launch_r2c_z(c->logn, src, in, c->delta, c->spec, c->tw, c->conv, c->stream)));
+  PM_TRY(dev(launch_fft_y(c->logn, c->spec, c->tw, false, c->stream)));
+  const double nn = (double)c->N;
+  const float gscale = (float)(-c->S * 2.0 / (nn * nn * nn));
+  PM_TRY(dev(launch_fft_x_green(c->logn, c->spec, c->tw, c->s2, gscale, c->stream)));
+  PM_TRY(dev(launch_fft_y(c->logn, c->spec, c->tw, true, c->stream)));
+  return dev(launch_c2r_z(c->logn, c->spec, c->tw, c->phi, c->stream));
+}
+
+pm_status run_qpot(pm_ctx* c, const float* delta, bool use_mass, bool energy) {
+  QConst qc = c->qc;
+  if (!use_mass) qc.fp64_below = -1.0;
+  return dev(launch_qpot(c->logn, c->fixed, energy, delta,
+                         static_cast<const long long*>(c->mass), c->phi, c->q, qc, c->partials,
+                         c->stream));
+}
+
+// deposit + Poisson + Q at the given positions, all into the workspace
+pm_status run_fields(pm_ctx* c, const void* pos, bool energy) {
+  PM_TRY(run_deposit(c, pos));
+  PM_TRY(run_poisson(c, c->fixed ? kSrcMass64 : kSrcAcc32, c->mass));
+  c->have_delta = true;
+  c->have_phi = true;
+  if (c->has_q || energy) PM_TRY(run_qpot(c, c->delta, true, energy));
+  c->have_q = c->has_q;
+  return PM_OK;
+}
+
+pm_status copy_out(pm_ctx* c, float* dst, const float* src) {
+  if (!dst || dst == src) return PM_OK;
+  return dev(hipMemcpyAsync(dst, src, 4 * c->ncell, hipMemcpyDeviceToDevice, c->stream));
+}
+
+}  // namespace
+
+extern "C" {
+
+pm_status pm_workspace_bytes(const pm_params* params, size_t* bytes) {
+  if (!bytes) return PM_EINVAL;
+  PM_TRY(check_params(params));
+  *bytes = layout_for(*params).total;
+  return PM_OK;
+}
+
+pm_status pm_init(const pm_params* params, void* d_workspace, size_t bytes, void* hip_stream,
+                  pm_ctx** out) {
+  if (!out || !d_workspace) return PM_EINVAL;
+  PM_TRY(check_params(params));
+  if (((uintptr_t)d_workspace) % kAlign != 0) return PM_EINVAL;
+  const Layout L = layout_for(*params);
+  if (bytes < L.total) return PM_ENOMEM;
+  pm_ctx* c = new (std::nothrow) pm_ctx();
+  if (!c) return PM_ENOMEM;
+  c->p = *params;
+  c->N = params->n_mesh;
+  c->logn = ilog2_exact(c->N);
+  c->B = 32 - c->logn;
+  c->np = params->n_part;
+  c->ncell = (size_t)c->N * c->N * c->N;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->fixed = params->precision == PM_FIXED32;
+  const double dx = params->box / c->N;
+  c->hm = params->hbar_over_m / (dx * dx);
+  c->has_q = c->hm > 0.0;
+  c->S = params->comoving ? 1.5 * params->omega_m * params->h0 * params->h0
+                          : params->four_pi_G_rhobar;
+  const int sh = kMassShift - 3 * c->logn;
+  const long long mbar = c->fixed ? (long long)(params->n_part) << (sh > 0 ? sh : 0) : 0;
+  c->conv.mbar = mbar;
+  c->conv.dmbar = (double)mbar;
+  c->conv.acc_norm = (float)((double)c->ncell / (double)c->np);
+  QConst& qc = c->qc;
+  qc.coef_d = -0.5 * c->hm * c->hm;
+  qc.coef = (float)qc.coef_d;
+  qc.floor_d = params->rho_floor;
+  qc.floor_f = (float)params->rho_floor;
+  qc.s_floor = (float)(sqrt(params->rho_floor) - 1.0);
+  qc.fp64_below = c->fixed ? params->rho_fp64_below : -1.0;
+  qc.mbar = mbar;
+  qc.inv_mbar = mbar ? 1.0 / (double)mbar : 0.0;
+  char* base = static_cast<char*>(d_workspace);
+  c->mass = base + L.mass;
+  c->delta = reinterpret_cast<float*>(base + L.delta);
+  c->phi = reinterpret_cast<float*>(base + L.phi);
+  c->q = reinterpret_cast<float*>(base + L.q);
+  c->spec = reinterpret_cast<float2*>(base + L.spec);
+  c->tw = reinterpret_cast<float2*>(base + L.tw);
+  c->s2 = reinterpret_cast<float*>(base + L.s2);
+  c->partials = reinterpret_cast<double*>(base + L.partials);
+  c->result = reinterpret_cast<double*>(base + L.result);
+  c->q_blocks = qpot_blocks(c->logn);
+  c->k_blocks = kinetic_blocks(c->np);
+  // constant tables, built in FP64 and rounded once
+  std::vector<float2> tw(c->N);
+  std::vector<float> s2(c->N);
+  for (int k = 0; k < c->N; ++k) {
+    const double ang = -2.0 * M_PI * k / c->N;
+    tw[k] = make_float2((float)cos(ang), (float)sin(ang));
+    const double sn = sin(M_PI * k / c->N);
+    s2[k] = (float)(4.0 * sn * sn);
+  }
+  hipError_t e = hipMemcpyAsync(c->tw, tw.data(), 8 * c->N, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->s2, s2.data(), 4 * c->N, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // host vectors die here
+  if (e == hipSuccess && !c->has_q) e = launch_fill_zero(c->q, 4 * c->ncell, c->stream);
+  if (e != hipSuccess) {
+    delete c;
+    return PM_EDEVICE;
+  }
+  *out = c;
+  return PM_OK;
+}
+
+pm_status pm_deposit(pm_ctx* c, const void* d_pos, float* d_delta) {
+  if (!c || !d_pos) return PM_EINVAL;
+  PM_TRY(run_deposit(c, d_pos));
+  // forward z-pass forms delta (and a spectrum the caller did not ask for);
+  // a standalone convert would move the same bytes minus the spectrum write
+  PM_TRY(dev(launch_r2c_z(c->logn, c->fixed ? kSrcMass64 : kSrcAcc32, c->mass, c->delta,
+                          c->spec, c->tw, c->conv, c->stream)));
+  c->have_delta = true;
+  c->have_phi = false;
+  c->fields_at_pos = false;
+  return copy_out(c, d_delta, c->delta);
+}
+
+pm_status pm_poisson(pm_ctx* c, const float* d_delta, float* d_phi) {
+  if (!c) return PM_EINVAL;
+  if (d_delta) {
+    PM_TRY(run_poisson(c, kSrcDelta, d_delta));
+  } else {
+    if (!c->have_delta) return PM_ESTATE;
+    PM_TRY(run_poisson(c, kSrcDelta, c->delta));
+  }
+  c->have_phi = true;
+  c->fields_at_pos = false;
+  return copy_out(c, d_phi, c->phi);
+}
+
+pm_status pm_qpot(pm_ctx* c, const float* d_delta, float* d_q) {
+  if (!c) return PM_EINVAL;
+  if (d_delta) {
+    PM_TRY(run_qpot(c, d_delta, false, false));
+  } else {
+    if (!c->have_delta) return PM_ESTATE;
+    PM_TRY(run_qpot(c, c->delta, c->fixed, false));
+  }
+  c->have_q = true;
+  c->fields_at_pos = false;
+  return copy_out(c, d_q, c->q);
+}
+
+pm_status pm_force(pm_ctx* c, const float* d_phi, const float* d_q, const void* d_pos,
+                   float* d_acc, double a) {
+  if (!c || !d_pos || !d_acc) return PM_EINVAL;
+  if (!(a > 0.0) || !isfinite(a)) return PM_EINVAL;
+  if (!c->p.comoving && a != 1.0) return PM_EINVAL;
+  const float* phi = d_phi ? d_phi : c->phi;
+  const float* q = d_q ? d_q : c->q;
+  if (!d_phi && !c->have_phi) return PM_ESTATE;
+  const bool use_q = d_q != nullptr || (c->has_q && c->have_q);
+  if (!d_q && c->has_q && !c->have_q) return PM_ESTATE;
+  return dev(launch_force(c->fixed, use_q, c->logn, d_pos, phi, q, c->np, (float)(1.0 / a),
+                          (float)(1.0 / (a * a)), d_acc, c->stream));
+}
+
+pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int32_t nsteps,
+                  int32_t flags) {
+  if (!c || !d_pos || !d_vel || !times) return PM_EINVAL;
+  if (nsteps < 1) return PM_EINVAL;
+  if (flags & ~PM_CONTINUE) return PM_EINVAL;
+  for (int s = 0; s <= nsteps; ++s) {
+    if (!isfinite(times[s])) return PM_EINVAL;
+    if (c->p.comoving && !(times[s] > 0.0)) return PM_EINVAL;
+    if (s > 0 && !(times[s] > times[s - 1])) return PM_EINVAL;
+  }
+  if (!((flags & PM_CONTINUE) && c->fields_at_pos)) PM_TRY(run_fields(c, d_pos, false));
+  c->fields_at_pos = false;
+  const double fdu = c->fixed ? ldexp(1.0, c->B) : 1.0;
+  Kick close = {0.0, 0.0};
+  for (int s = 0; s < nsteps; ++s) {
+    const double t0 = times[s], t1 = times[s + 1];
+    const double tm = midpoint(c->p, t0, t1);
+    const Kick open = kick(c->p, t0, tm);
+    GatherConst gc;
+    gc.fg = (float)(close.g + open.g);
+    gc.fq = (float)(close.q + open.q);
+    gc.fd_units = drift(c->p, t0, t1) * fdu;
+    PM_TRY(dev(launch_gather(c->fixed, c->has_q, true, c->logn, d_pos, d_vel, c->phi, c->q,
+                             c->np, gc, c->stream)));
+    PM_TRY(run_fields(c, d_pos, false));
+    close = kick(c->p, tm, t1);
+  }
+  GatherConst gc;
+  gc.fg = (float)close.g;
+  gc.fq = (float)close.q;
+  gc.fd_units = 0.0;
+  PM_TRY(dev(launch_gather(c->fixed, c->has_q, false, c->logn, d_pos, d_vel, c->phi, c->q,
+                           c->np, gc, c->stream)));
+  c->fields_at_pos = true;
+  return PM_OK;
+}
+
+pm_status pm_energy(pm_ctx* c, const void* d_pos, const float* d_vel, double a,
+                    pm_energies* out) {
+  if (!c || !d_pos || !d_vel || !out) return PM_EINVAL;
+  if (!(a > 0.0) || !isfinite(a)) return PM_EINVAL;
+  if (!c->p.comoving && a != 1.0) return PM_EINVAL;
+  PM_TRY(run_fields(c, d_pos, true));
+  c->fields_at_pos = false;
+  PM_TRY(dev(launch_reduce(c->partials, c->q_blocks, 2, c->result, c->stream)));
+  double* kp = c->partials + 2 * (size_t)c->q_blocks;
+  PM_TRY(dev(launch_kinetic(d_vel, c->np, kp, c->k_blocks, c->stream)));
+  PM_TRY(dev(launch_reduce(kp, c->k_blocks, 1, c->result + 2, c->stream)));
+  double host[3];
+  PM_TRY(dev(hipMemcpyAsync(host, c->result, sizeof(host), hipMemcpyDeviceToHost, c->stream)));
+  PM_TRY(dev(hipStreamSynchronize(c->stream)));
+  const double mp = (double)c->ncell / (double)c->np;
+  out->K = 0.5 * mp * host[2] / (a * a);
+  out->W = 0.5 * host[0] / a;
+  out->U = 0.5 * c->hm * c->hm * host[1] / (a * a);
+  out->E = out->K + out->W + out->U;
+  return PM_OK;
+}
+
+pm_status pm_destroy(pm_ctx* c) {
+  if (!c) return PM_EINVAL;
+  delete c;
+  return PM_OK;
+}
+
+const char* pm_strerror(pm_status s) {
+  switch (s) {
+    case PM_OK: return "ok";
+    case PM_EINVAL: return "invalid argument";
+    case PM_ENOMEM: return "workspace too small";
+    case PM_EDEVICE: return "HIP runtime or kernel launch error";
+    case PM_EUNSUPPORTED: return "unsupported mesh size (power of two in [16, 512])";
+    case PM_ESTATE: return "required fields not computed yet";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

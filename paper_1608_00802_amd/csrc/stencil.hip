@@ -1,0 +1,152 @@
+// Quantum pressure on the mesh, step (ii) of Sec. II A:
+//   Q_c = -(hbar/m)^2/2 * L7[sqrt R] / sqrt R,  R = max(rho, floor),
+// L7 the compact 7-point stencil; the comoving Q of Eq. (18) is Q_c / a^2.
+//
+// Fixed-point form ("s-form"): with rho = 1 + delta, s = sqrt R - 1 is formed
+// as delta / (1 + sqrt(1 + delta)), which keeps full FP32 relative precision
+// for small delta; L7[sqrt R] = L7[s] exactly since the constant cancels.
+// Cells with rho below a threshold recompute sqrt R and Q in FP64 from the
+// exact integer mass (the 1/sqrt(rho) division is ill-conditioned there).
+// Plain FP32 form: sqrt(R) and the stencil directly in FP32.
+//
+// With ENERGY, each block also writes FP64 partial sums of delta*phi (for the
+// potential energy) and of sum_d (sqrt R_{j+e_d} - sqrt R_j)^2 (gradient energy
+// K_rho of Eq. (6), forward differences); a single-block kernel reduces the
+// partials in a fixed order, so the totals are deterministic.
+#include "internal.h"
+
+namespace fdm {
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  // wave64 shuffle reduction, then across the block's waves through LDS
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+  __syncthreads();
+  return t;
+}
+
+template <int LOGN, bool FIXED, bool ENERGY>
+__global__ void __launch_bounds__(kBlock) k_qpot(const float* __restrict__ delta,
+                                                 const long long* __restrict__ mass,
+                                                 const float* __restrict__ phi,
+                                                 float* __restrict__ q, QConst qc,
+                                                 double* __restrict__ partials) {
+  constexpr int N = 1 << LOGN;
+  constexpr int MASK = N - 1;
+  const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  const int iz = (int)(i & MASK);
+  const int iy = (int)((i >> LOGN) & MASK);
+  const int ix = (int)(i >> (2 * LOGN));
+  const size_t row = i - iz;
+  const size_t zp = row + ((iz + 1) & MASK), zm = row + ((iz - 1) & MASK);
+  const size_t yp = ((size_t)ix * N + ((iy + 1) & MASK)) * N + iz;
+  const size_t ym = ((size_t)ix * N + ((iy - 1) & MASK)) * N + iz;
+  const size_t xp = ((size_t)((ix + 1) & MASK) * N + iy) * N + iz;
+  const size_t xm = ((size_t)((ix - 1) & MASK) * N + iy) * N + iz;
+  const float dc = delta[i];
+  const float dn[6] = {delta[xp], delta[xm], delta[yp], delta[ym], delta[zp], delta[zm]};
+  float sc, sn[6];
+  float qv;
+  if constexpr (FIXED) {
+    auto sfun = [&](float d) {
+      const float r = 1.0f + d;
+      return (r >= qc.floor_f) ? d / (1.0f + sqrtf(r)) : qc.s_floor;
+    };
+    sc = sfun(dc);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) sn[k] = sfun(dn[k]);
+    const float lap = ((sn[0] + sn[1]) + (sn[2] + sn[3]) + (sn[4] + sn[5])) - 6.0f * sc;
+    qv = qc.coef * lap / (1.0f + sc);
+    if ((double)(1.0f + dc) < qc.fp64_below) {
+      auto sd = [&](size_t j) {
+        double r = (double)mass[j] * qc.inv_mbar;
+        r = r > qc.floor_d ? r : qc.floor_d;
+        return sqrt(r);
+      };
+      const double c = sd(i);
+      const double lapd = ((sd(xp) + sd(xm)) + (sd(yp) + sd(ym)) + (sd(zp) + sd(zm))) - 6.0 * c;
+      qv = (float)(qc.coef_d * lapd / c);
+    }
+  } else {
+    auto sfun = [&](float d) {
+      const float r = 1.0f + d;
+      return sqrtf(r >= qc.floor_f ? r : qc.floor_f);
+    };
+    sc = sfun(dc);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) sn[k] = sfun(dn[k]);
+    const float lap = ((sn[0] + sn[1]) + (sn[2] + sn[3]) + (sn[4] + sn[5])) - 6.0f * sc;
+    qv = qc.coef * lap / sc;
+  }
+  q[i] = qv;
+  if constexpr (ENERGY) {
+    __shared__ double red[kBlock / 64];
+    const double w = (double)dc * (double)phi[i];
+    const double e0 = (double)(sn[0] - sc), e1 = (double)(sn[2] - sc), e2 = (double)(sn[4] - sc);
+    const double u = e0 * e0 + e1 * e1 + e2 * e2;
+    const double ws = block_sum(w, red);
+    const double us = block_sum(u, red);
+    if (threadIdx.x == 0) {
+      partials[2 * (size_t)blockIdx.x] = ws;
+      partials[2 * (size_t)blockIdx.x + 1] = us;
+    }
+  }
+}
+
+int qpot_blocks(int logn) { return (int)(((size_t)1 << (3 * logn)) / kBlock); }
+
+hipError_t launch_qpot(int logn, bool fixed, bool energy, const float* delta,
+                       const long long* mass, const float* phi, float* q, const QConst& qc,
+                       double* partials, hipStream_t s) {
+  const dim3 g((unsigned)qpot_blocks(logn));
+#define L_(LN)                                                                            \
+  {                                                                                       \
+    if (fixed && energy)                                                                  \
+      hipLaunchKernelGGL((k_qpot<LN, true, true>), g, dim3(kBlock), 0, s, delta, mass, phi, \
+                         q, qc, partials);                                                \
+    else if (fixed)                                                                       \
+      hipLaunchKernelGGL((k_qpot<LN, true, false>), g, dim3(kBlock), 0, s, delta, mass,   \
+                         phi, q, qc, partials);                                           \
+    else if (energy)                                                                      \
+      hipLaunchKernelGGL((k_qpot<LN, false, true>), g, dim3(kBlock), 0, s, delta, mass,   \
+                         phi, q, qc, partials);                                           \
+    else                                                                                  \
+      hipLaunchKernelGGL((k_qpot<LN, false, false>), g, dim3(kBlock), 0, s, delta, mass,  \
+                         phi, q, qc, partials);                                           \
+  }
+  FDM_LOGN_SWITCH(logn, L_)
+#undef L_
+  return hipGetLastError();
+}
+
+// Sum ncomp interleaved components of nblocks partials, fixed order.
+__global__ void __launch_bounds__(kBlock) k_reduce(const double* __restrict__ partials,
+                                                   int nblocks, int ncomp,
+                                                   double* __restrict__ out) {
+  __shared__ double red[kBlock];
+  for (int c = 0; c < ncomp; ++c) {
+    double t = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kBlock) t += partials[(size_t)b * ncomp + c];
+    red[threadIdx.x] = t;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[c] = red[0];
+    __syncthreads();
+  }
+}
+
+hipError_t launch_reduce(const double* partials, int nblocks, int ncomp, double* out,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, partials, nblocks, ncomp, out);
+  return hipGetLastError();
+}
+
+}  // namespace fdm

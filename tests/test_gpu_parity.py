@@ -1,0 +1,300 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Sizes span several tiles and ragged particle counts; tolerances are the
+stated targets: relative L2 error below 1e-5 on rho, phi and Q, position
+drift below 1e-4 cell after 100 steps of the static single-mode problem.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import lattice_cells, sine_mode_state, to_fixed, quantize_state, zeldovich_state
+
+from gpu_helpers import (TWO40, c0_setup, cosmo_setup, mass_mesh, periodic_diff,
+                         positions_cells, rel_l2, to_device)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pm(gpu):
+    import paper_1608_00802_amd as pm_mod
+    pm_mod.load_library()
+    return pm_mod
+
+
+def _ctx(pm, lp, gpu):
+    return pm.PMContext(lp, device=gpu)
+
+
+def _clustered_state(n, npart, seed, nclumps=6, width=1.5):
+    """Particles in a few Gaussian clumps plus a sparse background, so that
+    many cells are empty or nearly empty (exercises the floor and the FP64
+    path)."""
+    rng = np.random.default_rng(seed)
+    centres = rng.random((nclumps, 3)) * n
+    k = rng.integers(0, nclumps, npart)
+    pos = centres[k] + width * rng.standard_normal((npart, 3))
+    bg = rng.random(npart) < 0.15
+    pos[bg] = rng.random((int(bg.sum()), 3)) * n
+    pos %= n
+    vel = 0.01 * rng.standard_normal((npart, 3))
+    return quantize_state(pos, vel, n, {"kind": "clumps"})
+
+
+# ------------------------------------------------------------------ deposit
+
+@pytest.mark.parametrize("n,npart", [(16, 3001), (32, 32 ** 3), (64, 40 ** 3 + 17)])
+def test_deposit_exact_mass_and_parity(pm, gpu, n, npart):
+    import torch
+    rng = np.random.default_rng(n)
+    st = quantize_state(rng.random((npart, 3)) * n, np.zeros((npart, 3)), n, {})
+    lp = pm.make_params(n, npart, float(n))
+    ctx = _ctx(pm, lp, gpu)
+    pos, _ = to_device(st, gpu)
+    delta = torch.empty(n ** 3, dtype=torch.float32, device=gpu)
+    ctx.deposit(pos, delta)
+    torch.cuda.synchronize()
+    m = mass_mesh(ctx)
+    assert int(m.astype(np.int64).sum()) == npart * 2 ** 40      # exact, integer
+    assert m.min() >= 0
+    op = oracle.Params(n=n, box=float(n), S=1.0, hbar_m=0.0)
+    rho = oracle.deposit(st.pos, op)
+    mbar = npart * TWO40 / n ** 3
+    # integer weights are rounded to 2^-40 of a particle: <= 4 units per corner
+    assert np.max(np.abs(m / mbar - rho)) <= 8 * 4.0 / mbar + 1e-15
+    d = delta.cpu().numpy().reshape(n, n, n)
+    assert rel_l2(1.0 + d, rho) < 1e-7
+    assert rel_l2(d, rho - 1.0) < 1e-6
+
+
+def test_deposit_bitwise_order_independent(pm, gpu):
+    import torch
+    n = 32
+    st = zeldovich_state(n, 10.0, 0.5, seed=3, m_ev=1e-22)
+    lp = pm.make_params(n, st.npart, float(n))
+    ctx = _ctx(pm, lp, gpu)
+    pos, _ = to_device(st, gpu)
+    ctx.deposit(pos)
+    m0 = mass_mesh(ctx).copy()
+    ctx.deposit(pos)
+    assert np.array_equal(mass_mesh(ctx), m0)
+    perm = torch.from_numpy(np.random.default_rng(1).permutation(st.npart)).to(gpu)
+    ctx.deposit(pos[:, perm].contiguous())
+    assert np.array_equal(mass_mesh(ctx), m0)
+
+
+# ------------------------------------------------------------------ Poisson
+
+@pytest.mark.parametrize("n", [16, 32, 64, 128])
+def test_poisson_sine_closed_form(pm, gpu, n):
+    import torch
+    lp = pm.make_params(n, n ** 3, float(n), four_pi_G_rhobar=1.7)
+    ctx = _ctx(pm, lp, gpu)
+    x = np.arange(n)
+    m = (1, 2, 3) if n > 16 else (1, 2, 1)
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    arg = 2 * np.pi * (m[0] * X + m[1] * Y + m[2] * Z) / n
+    d = (0.2 * np.sin(arg)).astype(np.float32)
+    phi = torch.empty(n ** 3, dtype=torch.float32, device=gpu)
+    ctx.poisson(torch.from_numpy(d.ravel()).to(gpu), phi)
+    k2 = sum(4 * math.sin(math.pi * mm / n) ** 2 for mm in m)
+    expect = -1.7 * d.astype(np.float64) / k2
+    assert rel_l2(phi.cpu().numpy().reshape(n, n, n), expect) < 2e-6
+
+
+@pytest.mark.parametrize("n", [16, 32, 64, 128])
+def test_poisson_random_vs_oracle(pm, gpu, n):
+    import torch
+    rng = np.random.default_rng(100 + n)
+    d = rng.standard_normal((n, n, n)).astype(np.float32)
+    lp = pm.make_params(n, n ** 3, float(n), four_pi_G_rhobar=0.9)
+    ctx = _ctx(pm, lp, gpu)
+    phi = torch.empty(n ** 3, dtype=torch.float32, device=gpu)
+    ctx.poisson(torch.from_numpy(d.ravel()).to(gpu), phi)
+    op = oracle.Params(n=n, box=float(n), S=0.9, hbar_m=0.0)
+    dd = d.astype(np.float64)
+    ref = oracle.poisson(dd - dd.mean(), op)
+    assert rel_l2(phi.cpu().numpy().reshape(n, n, n), ref) < 1e-5
+
+
+# ------------------------------------------------------------------ Q
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_qpot_vs_oracle_smooth(pm, gpu, precision):
+    import torch
+    n = 64
+    st = zeldovich_state(n, 10.0, 0.3, seed=7, m_ev=1e-22)
+    lp, op = cosmo_setup(n, 10.0, 1e-22, precision=precision)
+    ctx = _ctx(pm, lp, gpu)
+    pos, _ = to_device(st, gpu, fp32_positions=(precision == 0))
+    q = torch.empty(n ** 3, dtype=torch.float32, device=gpu)
+    ctx.deposit(pos)
+    ctx.qpot(None, q)
+    rho = oracle.deposit(positions_cells(pos, n, precision == 0), op)
+    ref = oracle.qpot(rho, op)
+    err = rel_l2(q.cpu().numpy().reshape(n, n, n), ref)
+    assert err < (1e-5 if precision == 1 else 1e-3), err
+
+
+def test_qpot_near_empty_cells_fp64_path(pm, gpu):
+    import torch
+    n = 32
+    st = _clustered_state(n, 20000, seed=5)
+    lp, op = cosmo_setup(n, 5.0, 1e-22)
+    lp.n_part = st.npart
+    ctx = _ctx(pm, lp, gpu)
+    pos, _ = to_device(st, gpu)
+    q = torch.empty(n ** 3, dtype=torch.float32, device=gpu)
+    ctx.deposit(pos)
+    ctx.qpot(None, q)
+    rho = oracle.deposit(st.pos, op)
+    ref = oracle.qpot(rho, op)
+    got = q.cpu().numpy().reshape(n, n, n)
+    low = rho < 1e-3
+    assert low.sum() > 100 and (rho == 0).sum() > 10
+    assert rel_l2(got, ref) < 1e-5
+    assert rel_l2(got[~low], ref[~low]) < 1e-5
+    assert rel_l2(got[low], ref[low]) < 1e-5
+
+
+# ------------------------------------------------------------------ force, one step
+
+def test_force_vs_oracle(pm, gpu):
+    import torch
+    n = 64
+    st = zeldovich_state(n, 10.0, 0.2, seed=11, m_ev=1e-22)
+    lp, op = cosmo_setup(n, 10.0, 1e-22)
+    ctx = _ctx(pm, lp, gpu)
+    pos, _ = to_device(st, gpu)
+    acc = torch.empty((3, st.npart), dtype=torch.float32, device=gpu)
+    a = 0.2
+    ctx.deposit(pos)
+    ctx.poisson()
+    ctx.qpot()
+    ctx.force(pos, acc, a)
+    gphi, gq = oracle.forces(st.pos, op)
+    ref = gphi / a + gq / a ** 2
+    assert rel_l2(acc.cpu().numpy().T, ref) < 1e-5
+
+
+@pytest.mark.parametrize("a0,precision", [(0.01, 1), (0.3, 1), (0.3, 0)])
+def test_one_step_vs_oracle(pm, gpu, a0, precision):
+    import torch
+    n = 64
+    st = zeldovich_state(n, 10.0, a0, seed=1, m_ev=1e-22)
+    lp, op = cosmo_setup(n, 10.0, 1e-22, precision=precision)
+    ctx = _ctx(pm, lp, gpu)
+    fp32 = precision == 0
+    pos, vel = to_device(st, gpu, fp32_positions=fp32)
+    a1 = a0 * math.exp(math.log(100.0) / 500)
+    ctx.step(pos, vel, [a0, a1])
+    torch.cuda.synchronize()
+    x0 = positions_cells(torch.from_numpy(st.pos_f32) if fp32 else
+                         torch.from_numpy(st.pos_fixed.view(np.int32)), n, fp32)
+    x1, v1 = oracle.kdk_step(x0, st.vel, op, a0, a1)[:2]
+    xg = positions_cells(pos, n, fp32)
+    vg = vel.cpu().numpy().T.astype(np.float64)
+    dx = np.max(np.abs(periodic_diff(xg, x1, n)))
+    assert dx < (1e-5 if precision == 1 else 2e-4), dx
+    assert rel_l2(vg, v1) < (1e-5 if precision == 1 else 1e-3)
+    # fields at the new positions: the GPU's own x1 through the GPU, the
+    # same x1 through the oracle (kernel parity at x1)
+    dl = torch.empty(n ** 3, dtype=torch.float32, device=gpu)
+    ph = torch.empty_like(dl)
+    qq = torch.empty_like(dl)
+    ctx.deposit(pos, dl)
+    ctx.poisson(None, ph)
+    ctx.qpot(None, qq)
+    rho, delta, phi, q = oracle.fields(xg, op)
+    tol = 1e-5 if precision == 1 else 1e-3
+    assert rel_l2(1.0 + dl.cpu().numpy().reshape(n, n, n), rho) < tol
+    assert rel_l2(ph.cpu().numpy().reshape(n, n, n), phi) < tol
+    assert rel_l2(qq.cpu().numpy().reshape(n, n, n), q) < tol
+
+
+def test_step_continue_equals_single_call(pm, gpu):
+    import torch
+    n = 32
+    st = zeldovich_state(n, 10.0, 0.05, seed=2, m_ev=1e-22)
+    lp, _ = cosmo_setup(n, 10.0, 1e-22)
+    times = list(0.05 * np.exp(np.arange(11) * 0.01))
+    ctx = _ctx(pm, lp, gpu)
+    p1, v1 = to_device(st, gpu)
+    ctx.step(p1, v1, times)
+    p2, v2 = to_device(st, gpu)
+    ctx.step(p2, v2, times[:6])
+    ctx.step(p2, v2, times[5:], flags=pm.PM_CONTINUE)
+    torch.cuda.synchronize()
+    # the only difference: the split call closes and reopens the kick at a_5
+    # in two float adds instead of one -- positions agree to rounding
+    d = periodic_diff(positions_cells(p1, n), positions_cells(p2, n), n)
+    assert np.max(np.abs(d)) < 1e-6
+    assert rel_l2(v2.cpu().numpy(), v1.cpu().numpy()) < 1e-6
+
+
+# ------------------------------------------------------------------ static box, 100 steps
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_c0_drift_100_steps(pm, gpu, precision):
+    import torch
+    st = sine_mode_state(32, 2, 1e-3)
+    lp, op = c0_setup(precision)
+    ctx = _ctx(pm, lp, gpu)
+    fp32 = precision == 0
+    pos, vel = to_device(st, gpu, fp32_positions=fp32)
+    times = list(np.arange(101) * 0.01)
+    ctx.step(pos, vel, times)
+    torch.cuda.synchronize()
+    x0 = positions_cells(torch.from_numpy(st.pos_f32) if fp32 else
+                         torch.from_numpy(st.pos_fixed.view(np.int32)), 32, fp32)
+    xo, vo = oracle.run(x0, st.vel, op, times)
+    xg = positions_cells(pos, 32, fp32)
+    drift = np.max(np.abs(periodic_diff(xg, xo, 32)))
+    if precision == 1:
+        assert drift < 1e-4, drift
+    # linear theory: amplitude ratio 1.486711 (discrete dispersion + KDK)
+    q = lattice_cells(32, 32)
+    basis = np.sin(2 * np.pi * 2 * q[:, 0] / 32)
+    amp = periodic_diff(xg[:, 0], q[:, 0], 32) @ basis / (basis @ basis)
+    amp0 = periodic_diff(x0[:, 0], q[:, 0], 32) @ basis / (basis @ basis)
+    if precision == 1:
+        assert abs(amp / amp0 - 1.486711) < 1e-4
+    print(f"c0 precision={precision}: drift vs oracle {drift:.3e} cell, growth {amp / amp0:.7f}")
+
+
+# ------------------------------------------------------------------ energies
+
+def test_energy_vs_oracle(pm, gpu):
+    n = 32
+    st = zeldovich_state(n, 2.0, 0.1, seed=4, m_ev=2.5e-22)
+    lp, op = cosmo_setup(n, 2.0, 2.5e-22)
+    ctx = _ctx(pm, lp, gpu)
+    pos, vel = to_device(st, gpu)
+    a = 0.1
+    e = ctx.energy(pos, vel, a)
+    ref = oracle.energies(st.pos, st.vel, op, a)
+    for k in ("K", "W", "U"):
+        assert abs(e[k] - ref[k]) < 1e-5 * abs(ref[k]), (k, e[k], ref[k])
+
+
+def test_fixed_point_wrap_across_boundary(pm, gpu):
+    """Particles drifting through the box faces wrap exactly (fixed point)."""
+    import torch
+    n = 16
+    q = lattice_cells(n, n)
+    vel = np.zeros_like(q)
+    vel[:, 0] = 3.0      # 3 cells per time unit along x
+    vel[:, 2] = -1.25
+    st = quantize_state(q, vel, n, {})
+    lp = pm.make_params(n, n ** 3, float(n), four_pi_G_rhobar=0.0)
+    ctx = _ctx(pm, lp, gpu)
+    pos, v = to_device(st, gpu)
+    ctx.step(pos, v, [0.0, 1.0, 2.0, 3.0, 4.0])
+    torch.cuda.synchronize()
+    got = pos.cpu().numpy().view(np.uint32)
+    expect = to_fixed((q + 4.0 * vel) % n, n)
+    assert np.array_equal(got, expect)
