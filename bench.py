@@ -1,0 +1,213 @@
+#!/usr/bin/env python
+"""Throughput of one full particle-mesh step on one MI355X.
+
+A step is one pass of the whole hot path over the particle set: CIC deposit
+(integer, fixed-point), forward real FFT, Green's function, inverse FFT,
+quantum-pressure stencil and the fused gather-kick-drift (merged half-kicks).
+Workload: comoving box of 10 Mpc/h, 256^3 particles on a 256^3 mesh, boson
+mass 1e-22 eV, Omega_m = 0.3, h = 0.7, Zel'dovich initial conditions at
+a = 0.01 (seed 1), 32-bit fixed-point positions, FP32 FFT and stencils.
+Inputs are resident in HBM before the timed region.
+
+Prints one JSON line.  Also measured: the same workload from a clustered
+state (the same field evaluated at a = 0.5), per-kernel times from HIP events
+on the library's stream, and the FP64 oracle on the host as a CPU baseline.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-updates/s per full PM step at 256^3; p50/p99 run latency (served)"
+HBM_PEAK_GBS = 8000.0
+DLNA = math.log(100.0) / 500.0
+
+
+def alg_bytes(n: int, npart: int) -> dict:
+    """Algorithmic HBM bytes per launch of each kernel family (fixed form).
+
+    cells: N^3; spectrum: (N/2+1) N^2 complex64.  Each byte that a kernel
+    must read or write once: positions 12 B/particle (uint32 x3), velocities
+    12 B/particle, int64 mass 8 B/cell, float meshes 4 B/cell.
+    """
+    cells = n ** 3
+    spec = 8 * (n // 2 + 1) * n * n
+    return {
+        "fill_zero": 8 * cells,
+        "deposit": 12 * npart + 16 * cells,         # read positions, read+write mass once
+        "r2c_z": 8 * cells + 4 * cells + spec,      # mass in, delta and spectrum out
+        "fft_y": 2 * spec,
+        "fft_x_green": 2 * spec,
+        "fft_y_inv": 2 * spec,
+        "c2r_z": spec + 4 * cells,
+        "qpot": 8 * cells,                           # delta in, Q out
+        "gather_kick_drift": 48 * npart + 8 * cells,  # pos+vel in/out, phi and Q once
+        "kick": 36 * npart + 8 * cells,
+    }
+
+
+def make_state(n, a_eval):
+    from synth import zeldovich_state
+    return zeldovich_state(n, 10.0, 0.01, seed=1, m_ev=1e-22, a_eval=a_eval)
+
+
+def run_gpu(st, n, steps, warmup, a_start, kernel_pass=True):
+    import numpy as np
+    import torch
+
+    import paper_1608_00802_amd as pm
+    from synth import comoving_code_params
+
+    dev = torch.device("cuda:0")
+    hm = comoving_code_params(10.0, n, 1e-22, 0.7)["hbar_m_cells"] * (10.0 / n) ** 2
+    lp = pm.make_params(n, st.npart, 10.0, precision=pm.PM_FIXED32, comoving=True,
+                        omega_m=0.3, omega_l=0.7, h0=1.0, hbar_over_m=hm, rho_floor=1e-6,
+                        rho_fp64_below=1e-3)
+    ctx = pm.PMContext(lp, device=dev)
+    pos = torch.from_numpy(st.pos_fixed.view(np.int32).copy()).to(dev)
+    vel = torch.from_numpy(st.vel32.copy()).to(dev)
+    total = warmup + steps + (steps if kernel_pass else 0)
+    times = [a_start * math.exp(i * DLNA) for i in range(total + 1)]
+    torch.cuda.synchronize()
+    ctx.step(pos, vel, times[: warmup + 1])
+    torch.cuda.synchronize()
+    stream = ctx.stream
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    ctx.step(pos, vel, times[warmup: warmup + steps + 1], flags=pm.PM_CONTINUE)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = ev0.elapsed_time(ev1)
+    out = {"wall_s": wall, "event_ms": ev_ms, "np": st.npart}
+    if kernel_pass:
+        ctx.timing(True)
+        ctx.step(pos, vel, times[warmup + steps: warmup + 2 * steps + 1], flags=pm.PM_CONTINUE)
+        out["kernels"] = ctx.timing_read()
+        ctx.timing(False)
+    ok = bool(torch.isfinite(vel).all().item())
+    out["finite"] = ok
+    ctx.close()
+    return out
+
+
+def kernel_table(kern, n, npart):
+    ab = alg_bytes(n, npart)
+    rows = {}
+    for name, (launches, ms) in kern.items():
+        avg = ms / launches
+        row = {"launches": launches, "avg_ms": round(avg, 5)}
+        if name in ab:
+            row["alg_bytes"] = ab[name]
+            row["alg_GBs"] = round(ab[name] / (avg * 1e-3) / 1e9, 1)
+        rows[name] = row
+    return rows
+
+
+def cpu_baseline(st, n):
+    """FP64 oracle, one steady-state kick-drift-kick step on the full workload."""
+    import oracle
+    from synth import comoving_code_params
+    hm = comoving_code_params(10.0, n, 1e-22, 0.7)["hbar_m_cells"]
+    p = oracle.Params(n=n, box=float(n), S=1.5 * 0.3, hbar_m=hm, comoving=True,
+                      omega_m=0.3, omega_l=0.7, h0=1.0, rho_floor=1e-6)
+    a0 = 0.01
+    a1 = a0 * math.exp(DLNA)
+    acc0 = oracle.forces(st.pos, p)            # opening forces, untimed
+    t0 = time.perf_counter()
+    oracle.kdk_step(st.pos, st.vel, p, a0, a1, acc0)
+    dt = time.perf_counter() - t0
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        cores = os.cpu_count()
+    return {"value": st.npart / dt, "unit": "particle-updates/s", "cores": 1,
+            "cores_available": cores, "kind": "oracle",
+            "sample": f"one steady-state KDK step (force evaluation at the drifted positions, "
+                      f"both half-kicks, drift) of the FP64 NumPy oracle on the full {n}^3 "
+                      f"workload, single-threaded NumPy; {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-clustered", action="store_true")
+    ap.add_argument("--no-kernel-pass", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the single-GPU box is the whole measured job)", file=sys.stderr)
+        sys.exit(2)
+    n = args.n
+    st = make_state(n, None)
+    res = run_gpu(st, n, args.steps, args.warmup, 0.01, kernel_pass=not args.no_kernel_pass)
+    value = res["np"] * args.steps / res["wall_s"]
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["wall_s"] * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic: Zel'dovich initial conditions from a seeded Gaussian field",
+        "config": {
+            "workload": f"comoving 10 Mpc/h box, {n}^3 particles on a {n}^3 mesh, "
+                        "m = 1e-22 eV, Omega_m = 0.3, h = 0.7, Zel'dovich ICs at a = 0.01, "
+                        "fixed-point uint32 positions, FP32 FFT/stencils, int64 deposit",
+            "n_mesh": n,
+            "n_part": res["np"],
+            "a_start": 0.01,
+            "dlna_per_step": DLNA,
+            "event_ms_per_step": res["event_ms"] / args.steps,
+        },
+    }
+    if "kernels" in res:
+        table = kernel_table(res["kernels"], n, res["np"])
+        line["kernels"] = table
+        timed = {k: v for k, v in table.items() if "alg_bytes" in v}
+        dom = max(timed, key=lambda k: timed[k]["avg_ms"] * timed[k]["launches"])
+        ach = timed[dom]["alg_GBs"]
+        line["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                            "traffic": None}
+        step_bytes = sum(alg_bytes(n, res["np"])[k] for k in alg_bytes(n, res["np"]) if k != "kick")
+        line["step_alg_bytes"] = step_bytes
+        line["step_alg_GBs"] = round(step_bytes / (res["wall_s"] / args.steps) / 1e9, 1)
+    if not args.no_clustered:
+        stc = make_state(n, 0.5)
+        rc = run_gpu(stc, n, args.steps, args.warmup, 0.5, kernel_pass=not args.no_kernel_pass)
+        line["clustered"] = {
+            "state": "same field evaluated at a = 0.5 (Zel'dovich), stepped from a = 0.5",
+            "value": rc["np"] * args.steps / rc["wall_s"],
+            "ms_per_step": rc["wall_s"] * 1e3 / args.steps,
+        }
+        if "kernels" in rc:
+            line["clustered"]["kernels"] = kernel_table(rc["kernels"], n, rc["np"])
+        del stc
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(st, n)
+    line["finite"] = res["finite"]
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

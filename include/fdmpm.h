@@ -165,6 +165,22 @@ pm_status pm_step(pm_ctx* ctx, void* d_pos, float* d_vel, const double* times,
 pm_status pm_energy(pm_ctx* ctx, const void* d_pos, const float* d_vel,
                     double a, pm_energies* out);
 
+/* Per-kernel timing (observability).  While enabled, every kernel the
+ * context launches is bracketed by two HIP events recorded on its stream.
+ * pm_timing_enable(ctx, 1) clears the counters and starts recording;
+ * (ctx, 0) stops.  pm_timing_read synchronises the stream, folds all
+ * recorded events into per-kernel totals and writes up to max entries
+ * (*count receives the number written).  Event objects come from the HIP
+ * runtime and are reused; no device buffer is allocated. */
+typedef struct {
+  char name[32];      /* kernel family, e.g. "deposit", "fft_x_green" */
+  int64_t launches;   /* launches recorded since enable */
+  double total_ms;    /* summed event-to-event time */
+} pm_kernel_time;
+
+pm_status pm_timing_enable(pm_ctx* ctx, int32_t on);
+pm_status pm_timing_read(pm_ctx* ctx, pm_kernel_time* out, int32_t max, int32_t* count);
+
 /* Free the host-side context (no device memory is owned). */
 pm_status pm_destroy(pm_ctx* ctx);
 

@@ -22,5 +22,7 @@ from ._lib import (  # noqa: F401
     pm_poisson,
     pm_qpot,
     pm_step,
+    pm_timing_enable,
+    pm_timing_read,
     pm_workspace_bytes,
 )

@@ -21,7 +21,8 @@ PM_FP32, PM_FIXED32 = 0, 1
 PM_CONTINUE = 1
 
 EXPORTED = ("pm_workspace_bytes", "pm_init", "pm_deposit", "pm_poisson", "pm_qpot",
-            "pm_force", "pm_step", "pm_energy", "pm_destroy", "pm_strerror")
+            "pm_force", "pm_step", "pm_energy", "pm_timing_enable", "pm_timing_read",
+            "pm_destroy", "pm_strerror")
 
 
 class PMParams(ctypes.Structure):
@@ -44,6 +45,10 @@ class PMParams(ctypes.Structure):
 
 class PMEnergies(ctypes.Structure):
     _fields_ = [("K", c_double), ("W", c_double), ("U", c_double), ("E", c_double)]
+
+
+class PMKernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", c_int64), ("total_ms", c_double)]
 
 
 class PMError(RuntimeError):
@@ -74,6 +79,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "pm_force": ([c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double], c_int32),
         "pm_step": ([c_void_p, c_void_p, c_void_p, P(c_double), c_int32, c_int32], c_int32),
         "pm_energy": ([c_void_p, c_void_p, c_void_p, c_double, P(PMEnergies)], c_int32),
+        "pm_timing_enable": ([c_void_p, c_int32], c_int32),
+        "pm_timing_read": ([c_void_p, P(PMKernelTime), c_int32, P(c_int32)], c_int32),
         "pm_destroy": ([c_void_p], c_int32),
         "pm_strerror": ([c_int32], ctypes.c_char_p),
     }
@@ -156,6 +163,18 @@ def pm_energy(ctx: int, pos_ptr: int, vel_ptr: int, a: float) -> dict:
     return {"K": out.K, "W": out.W, "U": out.U, "E": out.E}
 
 
+def pm_timing_enable(ctx: int, on: bool) -> None:
+    _check(load_library().pm_timing_enable(c_void_p(ctx), int(bool(on))), "pm_timing_enable")
+
+
+def pm_timing_read(ctx: int) -> dict:
+    """{kernel family: (launches, total ms)} since the last pm_timing_enable."""
+    buf = (PMKernelTime * 32)()
+    n = c_int32(0)
+    _check(load_library().pm_timing_read(c_void_p(ctx), buf, 32, byref(n)), "pm_timing_read")
+    return {buf[i].name.decode(): (buf[i].launches, buf[i].total_ms) for i in range(n.value)}
+
+
 def pm_destroy(ctx: int) -> None:
     _check(load_library().pm_destroy(c_void_p(ctx)), "pm_destroy")
 
@@ -235,6 +254,12 @@ class PMContext:
 
     def energy(self, pos, vel, a=1.0):
         return pm_energy(self.ctx, self._pos(pos), self._vec(vel, "vel"), a)
+
+    def timing(self, on: bool):
+        pm_timing_enable(self.ctx, on)
+
+    def timing_read(self) -> dict:
+        return pm_timing_read(self.ctx)
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -12,6 +12,30 @@
 
 using namespace fdm;
 
+namespace {
+
+enum KernelClass : int {
+  kcFill, kcDeposit, kcR2C, kcFftY, kcFftX, kcFftYInv, kcC2R, kcQpot, kcGatherKD, kcKick,
+  kcForce, kcReduce, kcKinetic, kcCount
+};
+const char* const kKernelNames[kcCount] = {
+    "fill_zero", "deposit", "r2c_z", "fft_y", "fft_x_green", "fft_y_inv", "c2r_z",
+    "qpot", "gather_kick_drift", "kick", "force", "reduce", "kinetic"};
+
+struct Timer {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  struct Rec {
+    int kc;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> pending;
+  double ms[kcCount] = {};
+  int64_t launches[kcCount] = {};
+};
+
+}  // namespace
+
 struct pm_ctx {
   pm_params p;
   int N, logn, B;
@@ -41,6 +65,7 @@ struct pm_ctx {
   bool have_phi;
   bool have_q;
   bool fields_at_pos;  // phi, q correspond to the positions left by pm_step
+  Timer timer;
 };
 
 namespace {
@@ -119,6 +144,30 @@ pm_status dev(hipError_t e) { return e == hipSuccess ? PM_OK : PM_EDEVICE; }
     if (st_ != PM_OK) return st_;      \
   } while (0)
 
+hipEvent_t take_event(Timer& t) {
+  if (!t.pool.empty()) {
+    hipEvent_t e = t.pool.back();
+    t.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Launch through f(); with timing on, bracket it by two events on the stream.
+template <class F>
+pm_status timed(pm_ctx* c, int kc, F&& f) {
+  if (!c->timer.on) return dev(f());
+  hipEvent_t a = take_event(c->timer), b = take_event(c->timer);
+  if (!a || !b) return PM_EDEVICE;
+  if (hipEventRecord(a, c->stream) != hipSuccess) return PM_EDEVICE;
+  const hipError_t e = f();
+  if (hipEventRecord(b, c->stream) != hipSuccess) return PM_EDEVICE;
+  c->timer.pending.push_back({kc, a, b});
+  return dev(e);
+}
+
 // ------------------------------------------------------------ FP64 quadrature
 // Gauss-Legendre nodes/weights on [-1, 1] by Newton iteration on P_n.
 struct Gauss {
@@ -196,32 +245,39 @@ double midpoint(const pm_params& p, double t0, double t1) {
 
 // ------------------------------------------------------------ launch sequences
 pm_status run_deposit(pm_ctx* c, const void* pos) {
-  PM_TRY(dev(launch_fill_zero(c->mass, 8 * c->ncell, c->stream)));
-  if (c->fixed)
-    return dev(launch_deposit_fixed(static_cast<const uint32_t*>(pos), c->np, c->logn,
-                                    static_cast<unsigned long long*>(c->mass), c->stream));
-  return dev(launch_deposit_f32(static_cast<const float*>(pos), c->np, c->logn,
-                                static_cast<float*>(c->mass), c->stream));
+  PM_TRY(timed(c, kcFill, [&] { return launch_fill_zero(c->mass, 8 * c->ncell, c->stream); }));
+  return timed(c, kcDeposit, [&] {
+    if (c->fixed)
+      return launch_deposit_fixed(static_cast<const uint32_t*>(pos), c->np, c->logn,
+                                  static_cast<unsigned long long*>(c->mass), c->stream);
+    return launch_deposit_f32(static_cast<const float*>(pos), c->np, c->logn,
+                              static_cast<float*>(c->mass), c->stream);
+  });
 }
 
 // Forward z-pass from the context's mass mesh (or from a given delta),
 // remaining passes, potential into c->phi.
 pm_status run_poisson(pm_ctx* c, int src, const void* in) {
-  PM_TRY(dev(launch_r2c_z(c->logn, src, in, c->delta, c->spec, c->tw, c->conv, c->stream)));
-  PM_TRY(dev(launch_fft_y(c->logn, c->spec, c->tw, false, c->stream)));
+  PM_TRY(timed(c, kcR2C, [&] {
+    return launch_r2c_z(c->logn, src, in, c->delta, c->spec, c->tw, c->conv, c->stream);
+  }));
+  PM_TRY(timed(c, kcFftY, [&] { return launch_fft_y(c->logn, c->spec, c->tw, false, c->stream); }));
   const double nn = (double)c->N;
   const float gscale = (float)(-c->S * 2.0 / (nn * nn * nn));
-  PM_TRY(dev(launch_fft_x_green(c->logn, c->spec, c->tw, c->s2, gscale, c->stream)));
-  PM_TRY(dev(launch_fft_y(c->logn, c->spec, c->tw, true, c->stream)));
-  return dev(launch_c2r_z(c->logn, c->spec, c->tw, c->phi, c->stream));
+  PM_TRY(timed(c, kcFftX, [&] {
+    return launch_fft_x_green(c->logn, c->spec, c->tw, c->s2, gscale, c->stream);
+  }));
+  PM_TRY(timed(c, kcFftYInv, [&] { return launch_fft_y(c->logn, c->spec, c->tw, true, c->stream); }));
+  return timed(c, kcC2R, [&] { return launch_c2r_z(c->logn, c->spec, c->tw, c->phi, c->stream); });
 }
 
 pm_status run_qpot(pm_ctx* c, const float* delta, bool use_mass, bool energy) {
   QConst qc = c->qc;
   if (!use_mass) qc.fp64_below = -1.0;
-  return dev(launch_qpot(c->logn, c->fixed, energy, delta,
-                         static_cast<const long long*>(c->mass), c->phi, c->q, qc, c->partials,
-                         c->stream));
+  return timed(c, kcQpot, [&] {
+    return launch_qpot(c->logn, c->fixed, energy, delta, static_cast<const long long*>(c->mass),
+                       c->phi, c->q, qc, c->partials, c->stream);
+  });
 }
 
 // deposit + Poisson + Q at the given positions, all into the workspace
@@ -326,8 +382,10 @@ pm_status pm_deposit(pm_ctx* c, const void* d_pos, float* d_delta) {
   PM_TRY(run_deposit(c, d_pos));
   // forward z-pass forms delta (and a spectrum the caller did not ask for);
   // a standalone convert would move the same bytes minus the spectrum write
-  PM_TRY(dev(launch_r2c_z(c->logn, c->fixed ? kSrcMass64 : kSrcAcc32, c->mass, c->delta,
-                          c->spec, c->tw, c->conv, c->stream)));
+  PM_TRY(timed(c, kcR2C, [&] {
+    return launch_r2c_z(c->logn, c->fixed ? kSrcMass64 : kSrcAcc32, c->mass, c->delta, c->spec,
+                        c->tw, c->conv, c->stream);
+  }));
   c->have_delta = true;
   c->have_phi = false;
   c->fields_at_pos = false;
@@ -370,8 +428,10 @@ pm_status pm_force(pm_ctx* c, const float* d_phi, const float* d_q, const void* 
   if (!d_phi && !c->have_phi) return PM_ESTATE;
   const bool use_q = d_q != nullptr || (c->has_q && c->have_q);
   if (!d_q && c->has_q && !c->have_q) return PM_ESTATE;
-  return dev(launch_force(c->fixed, use_q, c->logn, d_pos, phi, q, c->np, (float)(1.0 / a),
-                          (float)(1.0 / (a * a)), d_acc, c->stream));
+  return timed(c, kcForce, [&] {
+    return launch_force(c->fixed, use_q, c->logn, d_pos, phi, q, c->np, (float)(1.0 / a),
+                        (float)(1.0 / (a * a)), d_acc, c->stream);
+  });
 }
 
 pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int32_t nsteps,
@@ -396,8 +456,10 @@ pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int
     gc.fg = (float)(close.g + open.g);
     gc.fq = (float)(close.q + open.q);
     gc.fd_units = drift(c->p, t0, t1) * fdu;
-    PM_TRY(dev(launch_gather(c->fixed, c->has_q, true, c->logn, d_pos, d_vel, c->phi, c->q,
-                             c->np, gc, c->stream)));
+    PM_TRY(timed(c, kcGatherKD, [&] {
+      return launch_gather(c->fixed, c->has_q, true, c->logn, d_pos, d_vel, c->phi, c->q, c->np,
+                           gc, c->stream);
+    }));
     PM_TRY(run_fields(c, d_pos, false));
     close = kick(c->p, tm, t1);
   }
@@ -405,8 +467,10 @@ pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int
   gc.fg = (float)close.g;
   gc.fq = (float)close.q;
   gc.fd_units = 0.0;
-  PM_TRY(dev(launch_gather(c->fixed, c->has_q, false, c->logn, d_pos, d_vel, c->phi, c->q,
-                           c->np, gc, c->stream)));
+  PM_TRY(timed(c, kcKick, [&] {
+    return launch_gather(c->fixed, c->has_q, false, c->logn, d_pos, d_vel, c->phi, c->q, c->np,
+                         gc, c->stream);
+  }));
   c->fields_at_pos = true;
   return PM_OK;
 }
@@ -418,10 +482,16 @@ pm_status pm_energy(pm_ctx* c, const void* d_pos, const float* d_vel, double a,
   if (!c->p.comoving && a != 1.0) return PM_EINVAL;
   PM_TRY(run_fields(c, d_pos, true));
   c->fields_at_pos = false;
-  PM_TRY(dev(launch_reduce(c->partials, c->q_blocks, 2, c->result, c->stream)));
+  PM_TRY(timed(c, kcReduce, [&] {
+    return launch_reduce(c->partials, c->q_blocks, 2, c->result, c->stream);
+  }));
   double* kp = c->partials + 2 * (size_t)c->q_blocks;
-  PM_TRY(dev(launch_kinetic(d_vel, c->np, kp, c->k_blocks, c->stream)));
-  PM_TRY(dev(launch_reduce(kp, c->k_blocks, 1, c->result + 2, c->stream)));
+  PM_TRY(timed(c, kcKinetic, [&] {
+    return launch_kinetic(d_vel, c->np, kp, c->k_blocks, c->stream);
+  }));
+  PM_TRY(timed(c, kcReduce, [&] {
+    return launch_reduce(kp, c->k_blocks, 1, c->result + 2, c->stream);
+  }));
   double host[3];
   PM_TRY(dev(hipMemcpyAsync(host, c->result, sizeof(host), hipMemcpyDeviceToHost, c->stream)));
   PM_TRY(dev(hipStreamSynchronize(c->stream)));
@@ -433,8 +503,57 @@ pm_status pm_energy(pm_ctx* c, const void* d_pos, const float* d_vel, double a,
   return PM_OK;
 }
 
+pm_status pm_timing_enable(pm_ctx* c, int32_t on) {
+  if (!c) return PM_EINVAL;
+  Timer& t = c->timer;
+  if (!t.pending.empty() && hipStreamSynchronize(c->stream) != hipSuccess) return PM_EDEVICE;
+  for (auto& r : t.pending) {
+    t.pool.push_back(r.a);
+    t.pool.push_back(r.b);
+  }
+  t.pending.clear();
+  for (int k = 0; k < kcCount; ++k) {
+    t.ms[k] = 0.0;
+    t.launches[k] = 0;
+  }
+  t.on = on != 0;
+  return PM_OK;
+}
+
+pm_status pm_timing_read(pm_ctx* c, pm_kernel_time* out, int32_t max, int32_t* count) {
+  if (!c || !count || max < 0 || (max > 0 && !out)) return PM_EINVAL;
+  Timer& t = c->timer;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return PM_EDEVICE;
+  for (auto& r : t.pending) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return PM_EDEVICE;
+    t.ms[r.kc] += ms;
+    t.launches[r.kc] += 1;
+    t.pool.push_back(r.a);
+    t.pool.push_back(r.b);
+  }
+  t.pending.clear();
+  int n = 0;
+  for (int k = 0; k < kcCount && n < max; ++k) {
+    if (t.launches[k] == 0) continue;
+    memset(out[n].name, 0, sizeof(out[n].name));
+    strncpy(out[n].name, kKernelNames[k], sizeof(out[n].name) - 1);
+    out[n].launches = t.launches[k];
+    out[n].total_ms = t.ms[k];
+    ++n;
+  }
+  *count = n;
+  return PM_OK;
+}
+
 pm_status pm_destroy(pm_ctx* c) {
   if (!c) return PM_EINVAL;
+  if (!c->timer.pending.empty()) (void)hipStreamSynchronize(c->stream);
+  for (auto& r : c->timer.pending) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : c->timer.pool) (void)hipEventDestroy(e);
   delete c;
   return PM_OK;
 }

@@ -3,11 +3,14 @@
 //
 // Fixed-point form: positions are uint32 u*2^32/N, so the top log2(N) bits are
 // the cell index and the low B = 32 - log2(N) bits the fraction.  Each particle
-// carries exactly 2^40 integer mass units; the eight trilinear weights are
-// formed from exact integer products (up to 3B <= 84 bits), rounded once to
-// 2^-40, and the corner with the largest weight takes the remainder, so every
-// particle deposits exactly 2^40 units.  Integer atomics commute, which makes
-// the mesh bitwise independent of particle order and of scheduling.
+// carries exactly 2^40 integer mass units.  A corner weight is
+// w_x w_y w_z / 2^(3B) of the particle: the product w_x w_y (< 2^51) is exact
+// in 64-bit integers and in FP64, the multiplication by w_z is one FP64
+// rounding (relative 2^-53), the scale to 2^40 units is an exact power of two
+// and rint gives the integer weight -- deterministic, within 0.5 + 2^-10 units
+// of the exact value.  The corner with the largest weight takes the remainder,
+// so every particle deposits exactly 2^40 units.  Integer atomics commute,
+// which makes the mesh bitwise independent of particle order and scheduling.
 //
 // Plain FP32 form: float positions and float atomics (order-dependent in the
 // last bits), kept as the comparison baseline.
@@ -31,16 +34,6 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
   return hipGetLastError();
 }
 
-// round(a*b / 2^S) for a < 2^57, b <= 2^28, 29 <= S <= 44: exact 128-bit product
-__device__ __forceinline__ unsigned long long mul_shift_round(unsigned long long a,
-                                                              unsigned long long b, int S) {
-  unsigned long long lo = a * b;
-  unsigned long long hi = __umul64hi(a, b);
-  unsigned long long lo2 = lo + (1ull << (S - 1));
-  hi += (lo2 < lo) ? 1ull : 0ull;
-  return (hi << (64 - S)) | (lo2 >> S);
-}
-
 template <int LOGN>
 __global__ void __launch_bounds__(kBlock) k_deposit_fixed(const uint32_t* __restrict__ px,
                                                           const uint32_t* __restrict__ py,
@@ -50,8 +43,9 @@ __global__ void __launch_bounds__(kBlock) k_deposit_fixed(const uint32_t* __rest
   constexpr int N = 1 << LOGN;
   constexpr uint32_t MASK = N - 1;
   constexpr int B = 32 - LOGN;
-  constexpr int S = 3 * B - kMassShift;
   constexpr unsigned long long ONE = 1ull << B;
+  // 2^(40 - 3B), exact
+  const double scale = ldexp(1.0, kMassShift - 3 * B);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += stride) {
     const uint32_t ux = px[i], uy = py[i], uz = pz[i];
@@ -66,7 +60,7 @@ __global__ void __launch_bounds__(kBlock) k_deposit_fixed(const uint32_t* __rest
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const unsigned long long wxy = wx[c >> 2] * wy[(c >> 1) & 1];
-      w[c] = mul_shift_round(wxy, wz[c & 1], S);
+      w[c] = (unsigned long long)rint((double)wxy * (double)wz[c & 1] * scale);
       sum += (c == big) ? 0ull : w[c];
     }
     // remainder to the heaviest corner: exactly 2^40 per particle

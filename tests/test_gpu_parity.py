@@ -47,7 +47,8 @@ def _clustered_state(n, npart, seed, nclumps=6, width=1.5):
 
 # ------------------------------------------------------------------ deposit
 
-@pytest.mark.parametrize("n,npart", [(16, 3001), (32, 32 ** 3), (64, 40 ** 3 + 17)])
+@pytest.mark.parametrize("n,npart", [(16, 3001), (32, 32 ** 3), (64, 40 ** 3 + 17),
+                                     (128, 100003), (256, 1 << 20), (512, 1 << 20)])
 def test_deposit_exact_mass_and_parity(pm, gpu, n, npart):
     import torch
     rng = np.random.default_rng(n)
@@ -89,7 +90,7 @@ def test_deposit_bitwise_order_independent(pm, gpu):
 
 # ------------------------------------------------------------------ Poisson
 
-@pytest.mark.parametrize("n", [16, 32, 64, 128])
+@pytest.mark.parametrize("n", [16, 32, 64, 128, 256, 512])
 def test_poisson_sine_closed_form(pm, gpu, n):
     import torch
     lp = pm.make_params(n, n ** 3, float(n), four_pi_G_rhobar=1.7)
@@ -106,7 +107,7 @@ def test_poisson_sine_closed_form(pm, gpu, n):
     assert rel_l2(phi.cpu().numpy().reshape(n, n, n), expect) < 2e-6
 
 
-@pytest.mark.parametrize("n", [16, 32, 64, 128])
+@pytest.mark.parametrize("n", [16, 32, 64, 128, 256])
 def test_poisson_random_vs_oracle(pm, gpu, n):
     import torch
     rng = np.random.default_rng(100 + n)
@@ -298,3 +299,60 @@ def test_fixed_point_wrap_across_boundary(pm, gpu):
     got = pos.cpu().numpy().view(np.uint32)
     expect = to_fixed((q + 4.0 * vel) % n, n)
     assert np.array_equal(got, expect)
+
+
+def test_comoving_20_steps_vs_oracle(pm, gpu):
+    """Twenty merged-kick comoving steps from a = 0.01 (10 Mpc/h cell size,
+    m = 1e-22 eV) against the oracle stepping the same schedule."""
+    import torch
+    n = 64
+    box = 10.0 * n / 256
+    st = zeldovich_state(n, box, 0.01, seed=1, m_ev=1e-22)
+    lp, op = cosmo_setup(n, box, 1e-22)
+    ctx = _ctx(pm, lp, gpu)
+    pos, vel = to_device(st, gpu)
+    times = list(0.01 * np.exp(np.arange(21) * math.log(100.0) / 500))
+    ctx.step(pos, vel, times)
+    torch.cuda.synchronize()
+    xo, vo = oracle.run(st.pos, st.vel, op, times)
+    xg = positions_cells(pos, n)
+    assert np.max(np.abs(periodic_diff(xg, xo, n))) < 1e-5
+    assert rel_l2(vel.cpu().numpy().T, vo) < 1e-5
+
+
+def test_full_size_256_fields_and_step(pm, gpu):
+    """The benchmark workload at full size (10 Mpc/h, 256^3 particles and
+    mesh, m = 1e-22 eV, Zel'dovich ICs at a = 0.01) in the launch
+    configuration the benchmark times: delta, phi, Q and the force at the
+    initial state, then positions and velocities after one step."""
+    import torch
+    n = 256
+    st = zeldovich_state(n, 10.0, 0.01, seed=1, m_ev=1e-22)
+    lp, op = cosmo_setup(n, 10.0, 1e-22)
+    ctx = _ctx(pm, lp, gpu)
+    pos, vel = to_device(st, gpu)
+    d = torch.empty(n ** 3, dtype=torch.float32, device=gpu)
+    ph = torch.empty_like(d)
+    qq = torch.empty_like(d)
+    acc = torch.empty((3, st.npart), dtype=torch.float32, device=gpu)
+    a0 = 0.01
+    ctx.deposit(pos, d)
+    ctx.poisson(None, ph)
+    ctx.qpot(None, qq)
+    ctx.force(pos, acc, a0)
+    torch.cuda.synchronize()
+    rho, delta, phi, q = oracle.fields(st.pos, op)
+    assert rel_l2(1.0 + d.cpu().numpy().reshape(n, n, n), rho) < 1e-5
+    assert rel_l2(d.cpu().numpy().reshape(n, n, n), delta) < 1e-5
+    assert rel_l2(ph.cpu().numpy().reshape(n, n, n), phi) < 1e-5
+    assert rel_l2(qq.cpu().numpy().reshape(n, n, n), q) < 1e-5
+    gphi = oracle.interp_cic(oracle.grad_central(phi, op), st.pos, op)
+    gq = oracle.interp_cic(oracle.grad_central(q, op), st.pos, op)
+    assert rel_l2(acc.cpu().numpy().T, gphi / a0 + gq / a0 ** 2) < 1e-5
+    del rho, delta, phi, q
+    a1 = a0 * math.exp(math.log(100.0) / 500)
+    ctx.step(pos, vel, [a0, a1])
+    torch.cuda.synchronize()
+    x1, v1, _ = oracle.kdk_step(st.pos, st.vel, op, a0, a1, (gphi, gq))
+    assert np.max(np.abs(periodic_diff(positions_cells(pos, n), x1, n))) < 1e-5
+    assert rel_l2(vel.cpu().numpy().T, v1) < 1e-5
