@@ -51,6 +51,9 @@ def alg_bytes(n: int, npart: int) -> dict:
         "qpot": 8 * cells,                           # delta in, Q out
         "gather_kick_drift": 48 * npart + 8 * cells,  # pos+vel in/out, phi and Q once
         "kick": 36 * npart + 8 * cells,
+        "sort_count": 12 * npart + 8 * npart,        # positions in, key and rank out
+        "sort_scatter": 8 * npart + 48 * npart,      # key, rank, pos+vel in, copies out
+        "sort_copy": 48 * npart,
     }
 
 
@@ -59,7 +62,7 @@ def make_state(n, a_eval):
     return zeldovich_state(n, 10.0, 0.01, seed=1, m_ev=1e-22, a_eval=a_eval)
 
 
-def run_gpu(st, n, steps, warmup, a_start, kernel_pass=True):
+def run_gpu(st, n, steps, warmup, a_start, kernel_pass=True, sort_every=10):
     import numpy as np
     import torch
 
@@ -77,14 +80,15 @@ def run_gpu(st, n, steps, warmup, a_start, kernel_pass=True):
     total = warmup + steps + (steps if kernel_pass else 0)
     times = [a_start * math.exp(i * DLNA) for i in range(total + 1)]
     torch.cuda.synchronize()
-    ctx.step(pos, vel, times[: warmup + 1])
+    sort_flag = pm.PM_SORT_EVERY(sort_every) if sort_every else 0
+    ctx.step(pos, vel, times[: warmup + 1], flags=sort_flag)
     torch.cuda.synchronize()
     stream = ctx.stream
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev0.record(stream)
-    ctx.step(pos, vel, times[warmup: warmup + steps + 1], flags=pm.PM_CONTINUE)
+    ctx.step(pos, vel, times[warmup: warmup + steps + 1], flags=pm.PM_CONTINUE | sort_flag)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -92,7 +96,8 @@ def run_gpu(st, n, steps, warmup, a_start, kernel_pass=True):
     out = {"wall_s": wall, "event_ms": ev_ms, "np": st.npart}
     if kernel_pass:
         ctx.timing(True)
-        ctx.step(pos, vel, times[warmup + steps: warmup + 2 * steps + 1], flags=pm.PM_CONTINUE)
+        ctx.step(pos, vel, times[warmup + steps: warmup + 2 * steps + 1],
+                 flags=pm.PM_CONTINUE | sort_flag)
         out["kernels"] = ctx.timing_read()
         ctx.timing(False)
     ok = bool(torch.isfinite(vel).all().item())
@@ -147,6 +152,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-clustered", action="store_true")
     ap.add_argument("--no-kernel-pass", action="store_true")
+    ap.add_argument("--sort-every", type=int, default=10,
+                    help="sort particles by tile every k steps inside the timed steps (0: never)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -154,7 +161,8 @@ def main():
         sys.exit(2)
     n = args.n
     st = make_state(n, None)
-    res = run_gpu(st, n, args.steps, args.warmup, 0.01, kernel_pass=not args.no_kernel_pass)
+    res = run_gpu(st, n, args.steps, args.warmup, 0.01, kernel_pass=not args.no_kernel_pass,
+                  sort_every=args.sort_every)
     value = res["np"] * args.steps / res["wall_s"]
     line = {
         "metric": METRIC,
@@ -178,6 +186,7 @@ def main():
             "a_start": 0.01,
             "dlna_per_step": DLNA,
             "event_ms_per_step": res["event_ms"] / args.steps,
+            "sort_every": args.sort_every,
         },
     }
     if "kernels" in res:
@@ -189,12 +198,16 @@ def main():
         line["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
                             "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                             "traffic": None}
-        step_bytes = sum(alg_bytes(n, res["np"])[k] for k in alg_bytes(n, res["np"]) if k != "kick")
+        ab = alg_bytes(n, res["np"])
+        per_step = ("fill_zero", "deposit", "r2c_z", "fft_y", "fft_x_green", "fft_y_inv", "c2r_z",
+                    "qpot", "gather_kick_drift")
+        step_bytes = sum(ab[k] for k in per_step)
         line["step_alg_bytes"] = step_bytes
         line["step_alg_GBs"] = round(step_bytes / (res["wall_s"] / args.steps) / 1e9, 1)
     if not args.no_clustered:
         stc = make_state(n, 0.5)
-        rc = run_gpu(stc, n, args.steps, args.warmup, 0.5, kernel_pass=not args.no_kernel_pass)
+        rc = run_gpu(stc, n, args.steps, args.warmup, 0.5, kernel_pass=not args.no_kernel_pass,
+                     sort_every=args.sort_every)
         line["clustered"] = {
             "state": "same field evaluated at a = 0.5 (Zel'dovich), stepped from a = 0.5",
             "value": rc["np"] * args.steps / rc["wall_s"],

@@ -104,6 +104,11 @@ typedef struct pm_ctx pm_ctx;
                           positions passed in (left by the previous pm_step
                           on this context, with unchanged positions): skip
                           the opening force evaluation */
+/* Sort the particles by tile (as pm_sort, without ids) before every k-th
+ * step of the call, starting with the first; k in 1..65535.  Particle order
+ * then changes; use pm_sort with an id array between calls to track
+ * particles. */
+#define PM_SORT_EVERY(k) ((((int32_t)(k)) & 0xffff) << 8)
 
 /* Bytes of device workspace a context with these parameters needs.  Pure
  * host function, no device access.  Returns PM_EINVAL / PM_EUNSUPPORTED for
@@ -158,6 +163,16 @@ pm_status pm_force(pm_ctx* ctx, const float* d_phi, const float* d_q,
  * the final positions. */
 pm_status pm_step(pm_ctx* ctx, void* d_pos, float* d_vel, const double* times,
                   int32_t nsteps, int32_t flags);
+
+/* Reorder the particles in place by mesh tile (4 x 4 x 32 cells; counting
+ * sort, order inside a tile unspecified) and remember the tile ranges.
+ * Afterwards the deposit and the gather stage each tile's mesh window in
+ * LDS.  Positions and velocities are permuted together; d_ids (int32 [Np],
+ * may be NULL) is permuted alongside so callers can track particles.  No
+ * result depends on the order: particles that leave their tile later are
+ * handled by a direct path, and the integer deposit is order-independent.
+ * Call again every few steps as particles move. */
+pm_status pm_sort(pm_ctx* ctx, void* d_pos, float* d_vel, int32_t* d_ids);
 
 /* K, W, U, E of the synchronised state (d_pos, d_vel) at scale factor a
  * (1 in a static box).  Recomputes delta and phi; blocks until done.

@@ -9,6 +9,7 @@ from ._lib import (  # noqa: F401
     PM_CONTINUE,
     PM_FIXED32,
     PM_FP32,
+    PM_SORT_EVERY,
     PMContext,
     PMError,
     PMParams,
@@ -21,6 +22,7 @@ from ._lib import (  # noqa: F401
     pm_init,
     pm_poisson,
     pm_qpot,
+    pm_sort,
     pm_step,
     pm_timing_enable,
     pm_timing_read,

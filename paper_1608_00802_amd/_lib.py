@@ -20,8 +20,12 @@ PM_OK, PM_EINVAL, PM_ENOMEM, PM_EDEVICE, PM_EUNSUPPORTED, PM_ESTATE = 0, -1, -2,
 PM_FP32, PM_FIXED32 = 0, 1
 PM_CONTINUE = 1
 
+
+def PM_SORT_EVERY(k: int) -> int:
+    return (int(k) & 0xffff) << 8
+
 EXPORTED = ("pm_workspace_bytes", "pm_init", "pm_deposit", "pm_poisson", "pm_qpot",
-            "pm_force", "pm_step", "pm_energy", "pm_timing_enable", "pm_timing_read",
+            "pm_force", "pm_step", "pm_sort", "pm_energy", "pm_timing_enable", "pm_timing_read",
             "pm_destroy", "pm_strerror")
 
 
@@ -78,6 +82,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "pm_qpot": ([c_void_p, c_void_p, c_void_p], c_int32),
         "pm_force": ([c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double], c_int32),
         "pm_step": ([c_void_p, c_void_p, c_void_p, P(c_double), c_int32, c_int32], c_int32),
+        "pm_sort": ([c_void_p, c_void_p, c_void_p, c_void_p], c_int32),
         "pm_energy": ([c_void_p, c_void_p, c_void_p, c_double, P(PMEnergies)], c_int32),
         "pm_timing_enable": ([c_void_p, c_int32], c_int32),
         "pm_timing_read": ([c_void_p, P(PMKernelTime), c_int32, P(c_int32)], c_int32),
@@ -154,6 +159,11 @@ def pm_step(ctx: int, pos_ptr: int, vel_ptr: int, times, flags: int = 0) -> None
     arr = (c_double * len(t))(*t)
     _check(load_library().pm_step(c_void_p(ctx), c_void_p(pos_ptr), c_void_p(vel_ptr), arr,
                                   len(t) - 1, int(flags)), "pm_step")
+
+
+def pm_sort(ctx: int, pos_ptr: int, vel_ptr: int, ids_ptr: int | None) -> None:
+    _check(load_library().pm_sort(c_void_p(ctx), c_void_p(pos_ptr), c_void_p(vel_ptr),
+                                  c_void_p(ids_ptr)), "pm_sort")
 
 
 def pm_energy(ctx: int, pos_ptr: int, vel_ptr: int, a: float) -> dict:
@@ -251,6 +261,16 @@ class PMContext:
         if len(times) < 2 or any(not math.isfinite(float(t)) for t in times):
             raise ValueError("times: need at least two finite values")
         pm_step(self.ctx, self._pos(pos), self._vec(vel, "vel"), times, flags)
+
+    def sort(self, pos, vel, ids=None):
+        torch = self.torch
+        ip = None
+        if ids is not None:
+            if ids.dtype != torch.int32 or ids.device != self.device or not ids.is_contiguous() \
+                    or tuple(ids.shape) != (self.np,):
+                raise ValueError(f"ids: need contiguous int32 [{self.np}] on {self.device}")
+            ip = ids.data_ptr()
+        pm_sort(self.ctx, self._pos(pos), self._vec(vel, "vel"), ip)
 
     def energy(self, pos, vel, a=1.0):
         return pm_energy(self.ctx, self._pos(pos), self._vec(vel, "vel"), a)

@@ -16,11 +16,12 @@ namespace {
 
 enum KernelClass : int {
   kcFill, kcDeposit, kcR2C, kcFftY, kcFftX, kcFftYInv, kcC2R, kcQpot, kcGatherKD, kcKick,
-  kcForce, kcReduce, kcKinetic, kcCount
+  kcForce, kcReduce, kcKinetic, kcSortCount, kcSortScan, kcSortScatter, kcSortCopy, kcCount
 };
 const char* const kKernelNames[kcCount] = {
     "fill_zero", "deposit", "r2c_z", "fft_y", "fft_x_green", "fft_y_inv", "c2r_z",
-    "qpot", "gather_kick_drift", "kick", "force", "reduce", "kinetic"};
+    "qpot", "gather_kick_drift", "kick", "force", "reduce", "kinetic", "sort_count",
+    "sort_scan", "sort_scatter", "sort_copy"};
 
 struct Timer {
   bool on = false;
@@ -59,6 +60,15 @@ struct pm_ctx {
   float* s2;
   double* partials;  // energy partial sums
   double* result;    // reduced energies (device)
+  unsigned* tile_counts;
+  unsigned* tile_start;  // [tiles + 1], valid once sorted
+  unsigned* sort_key;
+  unsigned* sort_rank;
+  uint32_t* pos_tmp;
+  float* vel_tmp;
+  int* ids_tmp;
+  int tiles;
+  bool sorted;       // tile_start describes a partition of the particles by tile
   int q_blocks;
   int k_blocks;
   bool have_delta;   // delta in the workspace was made by pm_deposit
@@ -81,7 +91,8 @@ int ilog2_exact(int n) {
 }
 
 struct Layout {
-  size_t mass, delta, phi, q, spec, tw, s2, partials, result, total;
+  size_t mass, delta, phi, q, spec, tw, s2, partials, result, tile_counts, tile_start, sort_key,
+      sort_rank, pos_tmp, vel_tmp, ids_tmp, total;
 };
 
 Layout layout_for(const pm_params& p) {
@@ -104,6 +115,16 @@ Layout layout_for(const pm_params& p) {
   const size_t qb = nc / kBlock;
   L.partials = take(8 * (2 * qb + 1024));
   L.result = take(8 * 16);
+  const int logn = ilog2_exact(p.n_mesh);
+  const size_t tiles = logn > 0 ? (size_t)tile_count(logn) : 1;
+  const size_t np = (size_t)(p.n_part > 0 ? p.n_part : 1);
+  L.tile_counts = take(4 * tiles);
+  L.tile_start = take(4 * (tiles + 1));
+  L.sort_key = take(4 * np);
+  L.sort_rank = take(4 * np);
+  L.pos_tmp = take(12 * np);
+  L.vel_tmp = take(12 * np);
+  L.ids_tmp = take(4 * np);
   L.total = off;
   return L;
 }
@@ -247,9 +268,16 @@ double midpoint(const pm_params& p, double t0, double t1) {
 pm_status run_deposit(pm_ctx* c, const void* pos) {
   PM_TRY(timed(c, kcFill, [&] { return launch_fill_zero(c->mass, 8 * c->ncell, c->stream); }));
   return timed(c, kcDeposit, [&] {
+    if (c->fixed && c->sorted)
+      return launch_deposit_fixed_tiled(static_cast<const uint32_t*>(pos), c->np, c->logn,
+                                        c->tile_start, static_cast<unsigned long long*>(c->mass),
+                                        c->stream);
     if (c->fixed)
       return launch_deposit_fixed(static_cast<const uint32_t*>(pos), c->np, c->logn,
                                   static_cast<unsigned long long*>(c->mass), c->stream);
+    if (c->sorted)
+      return launch_deposit_f32_tiled(static_cast<const float*>(pos), c->np, c->logn,
+                                      c->tile_start, static_cast<float*>(c->mass), c->stream);
     return launch_deposit_f32(static_cast<const float*>(pos), c->np, c->logn,
                               static_cast<float*>(c->mass), c->stream);
   });
@@ -299,6 +327,8 @@ pm_status copy_out(pm_ctx* c, float* dst, const float* src) {
 }  // namespace
 
 extern "C" {
+
+pm_status pm_sort(pm_ctx* c, void* d_pos, float* d_vel, int32_t* d_ids);
 
 pm_status pm_workspace_bytes(const pm_params* params, size_t* bytes) {
   if (!bytes) return PM_EINVAL;
@@ -353,6 +383,15 @@ pm_status pm_init(const pm_params* params, void* d_workspace, size_t bytes, void
   c->s2 = reinterpret_cast<float*>(base + L.s2);
   c->partials = reinterpret_cast<double*>(base + L.partials);
   c->result = reinterpret_cast<double*>(base + L.result);
+  c->tile_counts = reinterpret_cast<unsigned*>(base + L.tile_counts);
+  c->tile_start = reinterpret_cast<unsigned*>(base + L.tile_start);
+  c->sort_key = reinterpret_cast<unsigned*>(base + L.sort_key);
+  c->sort_rank = reinterpret_cast<unsigned*>(base + L.sort_rank);
+  c->pos_tmp = reinterpret_cast<uint32_t*>(base + L.pos_tmp);
+  c->vel_tmp = reinterpret_cast<float*>(base + L.vel_tmp);
+  c->ids_tmp = reinterpret_cast<int*>(base + L.ids_tmp);
+  c->tiles = tile_count(c->logn);
+  c->sorted = false;
   c->q_blocks = qpot_blocks(c->logn);
   c->k_blocks = kinetic_blocks(c->np);
   // constant tables, built in FP64 and rounded once
@@ -438,7 +477,8 @@ pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int
                   int32_t flags) {
   if (!c || !d_pos || !d_vel || !times) return PM_EINVAL;
   if (nsteps < 1) return PM_EINVAL;
-  if (flags & ~PM_CONTINUE) return PM_EINVAL;
+  if (flags & ~(PM_CONTINUE | PM_SORT_EVERY(0xffff))) return PM_EINVAL;
+  const int sort_every = (flags >> 8) & 0xffff;
   for (int s = 0; s <= nsteps; ++s) {
     if (!isfinite(times[s])) return PM_EINVAL;
     if (c->p.comoving && !(times[s] > 0.0)) return PM_EINVAL;
@@ -452,13 +492,14 @@ pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int
     const double t0 = times[s], t1 = times[s + 1];
     const double tm = midpoint(c->p, t0, t1);
     const Kick open = kick(c->p, t0, tm);
+    if (sort_every > 0 && s % sort_every == 0) PM_TRY(pm_sort(c, d_pos, d_vel, nullptr));
     GatherConst gc;
     gc.fg = (float)(close.g + open.g);
     gc.fq = (float)(close.q + open.q);
     gc.fd_units = drift(c->p, t0, t1) * fdu;
     PM_TRY(timed(c, kcGatherKD, [&] {
       return launch_gather(c->fixed, c->has_q, true, c->logn, d_pos, d_vel, c->phi, c->q, c->np,
-                           gc, c->stream);
+                           gc, c->sorted ? c->tile_start : nullptr, c->stream);
     }));
     PM_TRY(run_fields(c, d_pos, false));
     close = kick(c->p, tm, t1);
@@ -469,9 +510,39 @@ pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int
   gc.fd_units = 0.0;
   PM_TRY(timed(c, kcKick, [&] {
     return launch_gather(c->fixed, c->has_q, false, c->logn, d_pos, d_vel, c->phi, c->q, c->np,
-                         gc, c->stream);
+                         gc, c->sorted ? c->tile_start : nullptr, c->stream);
   }));
   c->fields_at_pos = true;
+  return PM_OK;
+}
+
+pm_status pm_sort(pm_ctx* c, void* d_pos, float* d_vel, int32_t* d_ids) {
+  if (!c || !d_pos || !d_vel) return PM_EINVAL;
+  const size_t cbytes = (4 * (size_t)c->tiles + 15) & ~(size_t)15;
+  PM_TRY(timed(c, kcFill, [&] { return launch_fill_zero(c->tile_counts, cbytes, c->stream); }));
+  PM_TRY(timed(c, kcSortCount, [&] {
+    return launch_sort_count(c->fixed, d_pos, c->np, c->logn, c->tile_counts, c->sort_key,
+                             c->sort_rank, c->stream);
+  }));
+  PM_TRY(timed(c, kcSortScan, [&] {
+    return launch_sort_scan(c->tile_counts, c->tiles, c->tile_start, c->stream);
+  }));
+  PM_TRY(timed(c, kcSortScatter, [&] {
+    return launch_sort_scatter(d_pos, d_vel, d_ids, c->np, c->sort_key, c->sort_rank,
+                               c->tile_start, c->pos_tmp, c->vel_tmp, c->ids_tmp, c->stream);
+  }));
+  PM_TRY(timed(c, kcSortCopy, [&] {
+    hipError_t e = hipMemcpyAsync(d_pos, c->pos_tmp, 12 * (size_t)c->np,
+                                  hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d_vel, c->vel_tmp, 12 * (size_t)c->np, hipMemcpyDeviceToDevice,
+                         c->stream);
+    if (e == hipSuccess && d_ids)
+      e = hipMemcpyAsync(d_ids, c->ids_tmp, 4 * (size_t)c->np, hipMemcpyDeviceToDevice,
+                         c->stream);
+    return e;
+  }));
+  c->sorted = true;
   return PM_OK;
 }
 

@@ -23,6 +23,14 @@ namespace fdm {
 constexpr int kBlock = 256;               // threads per block of the streaming kernels
 constexpr int kMassShift = 40;            // one particle = 2^40 integer mass units
 
+// Particle tiles of the sort, the tiled deposit and the tiled gather:
+// 2^kTileLX x 2^kTileLY x 2^kTileLZ cells (z clamped to the mesh size).
+constexpr int kTileLX = 2, kTileLY = 2, kTileLZ = 5;
+__host__ __device__ constexpr int tile_lz(int logn) { return logn < kTileLZ ? logn : kTileLZ; }
+__host__ __device__ constexpr int tile_count(int logn) {
+  return (1 << (logn - kTileLX)) * (1 << (logn - kTileLY)) * (1 << (logn - tile_lz(logn)));
+}
+
 // Sources of the forward z-pass.
 enum ZSource : int {
   kSrcMass64 = 0,   // exact integer mass (fixed-point form)
@@ -59,6 +67,20 @@ hipError_t launch_deposit_fixed(const uint32_t* pos, int64_t np, int logn,
                                 unsigned long long* mass, hipStream_t s);
 hipError_t launch_deposit_f32(const float* pos, int64_t np, int logn, float* acc,
                               hipStream_t s);
+// tiled variants: particles sorted by tile, tile ranges start[0..tiles]
+hipError_t launch_deposit_fixed_tiled(const uint32_t* pos, int64_t np, int logn,
+                                      const unsigned* start, unsigned long long* mass,
+                                      hipStream_t s);
+hipError_t launch_deposit_f32_tiled(const float* pos, int64_t np, int logn,
+                                    const unsigned* start, float* acc, hipStream_t s);
+
+// ---- sort.hip
+hipError_t launch_sort_count(bool fixed, const void* pos, int64_t np, int logn,
+                             unsigned* counts, unsigned* key, unsigned* rank, hipStream_t s);
+hipError_t launch_sort_scan(const unsigned* counts, int n, unsigned* start, hipStream_t s);
+hipError_t launch_sort_scatter(const void* pos, const float* vel, const int* ids, int64_t np,
+                               const unsigned* key, const unsigned* rank, const unsigned* start,
+                               uint32_t* pos_out, float* vel_out, int* ids_out, hipStream_t s);
 
 // ---- fft.hip
 // Forward transform of the density contrast and Poisson solve, written as
@@ -83,7 +105,7 @@ hipError_t launch_reduce(const double* partials, int nblocks, int ncomp, double*
 // ---- gather.hip
 hipError_t launch_gather(bool fixed, bool has_q, bool drift, int logn, void* pos,
                          float* vel, const float* phi, const float* q, int64_t np,
-                         const GatherConst& gc, hipStream_t s);
+                         const GatherConst& gc, const unsigned* tile_start, hipStream_t s);
 hipError_t launch_force(bool fixed, bool has_q, int logn, const void* pos,
                         const float* phi, const float* q, int64_t np, float fg, float fq,
                         float* acc, hipStream_t s);

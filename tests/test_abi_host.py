@@ -50,9 +50,12 @@ def test_workspace_bytes(lib):
     for n in (16, 32, 64, 128, 256, 512):
         b = _lib.pm_workspace_bytes(_params(n_mesh=n, n_part=n ** 3))
         cells = n ** 3
-        # int64 mass + delta + phi + Q + half spectrum, plus small tables
-        assert b >= 8 * cells + 12 * cells + 8 * (n // 2 + 1) * n * n
-        assert b < 8 * cells + 12 * cells + 8 * (n // 2 + 1) * n * n + 8 * 2 * cells // 256 + 65536
+        npart = n ** 3
+        # int64 mass + delta + phi + Q + half spectrum, the particle sort
+        # (key, rank, position/velocity/id copies: 36 B per particle), tables
+        need = 8 * cells + 12 * cells + 8 * (n // 2 + 1) * n * n + 36 * npart
+        assert b >= need
+        assert b < need + 8 * 2 * cells // 256 + 8 * cells // 128 + 65536
         assert b % 256 == 0
 
 

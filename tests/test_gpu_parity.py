@@ -356,3 +356,110 @@ def test_full_size_256_fields_and_step(pm, gpu):
     x1, v1, _ = oracle.kdk_step(st.pos, st.vel, op, a0, a1, (gphi, gq))
     assert np.max(np.abs(periodic_diff(positions_cells(pos, n), x1, n))) < 1e-5
     assert rel_l2(vel.cpu().numpy().T, v1) < 1e-5
+
+
+# ------------------------------------------------------------------ sort + tiled kernels
+
+def test_sort_is_permutation_by_tile(pm, gpu):
+    import torch
+    n = 64
+    st = zeldovich_state(n, 10.0, 0.5, seed=8, m_ev=1e-22)
+    lp, _ = cosmo_setup(n, 10.0, 1e-22)
+    ctx = _ctx(pm, lp, gpu)
+    pos, vel = to_device(st, gpu)
+    ids = torch.arange(st.npart, dtype=torch.int32, device=gpu)
+    ctx.sort(pos, vel, ids)
+    torch.cuda.synchronize()
+    idn = ids.cpu().numpy()
+    assert np.array_equal(np.sort(idn), np.arange(st.npart))
+    assert np.array_equal(pos.cpu().numpy(), st.pos_fixed.view(np.int32)[:, idn])
+    assert np.array_equal(vel.cpu().numpy(), st.vel32[:, idn])
+    cell = pos.cpu().numpy().view(np.uint32) >> (32 - 6)
+    key = ((cell[0] >> 2) * (n // 4) + (cell[1] >> 2)) * (n // 32) + (cell[2] >> 5)
+    assert np.all(np.diff(key.astype(np.int64)) >= 0)
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_tiled_deposit_equals_direct(pm, gpu, precision):
+    """Tiled (LDS) deposit after a sort, with some particles moved out of
+    their tiles afterwards, against the direct deposit of the same particles:
+    bitwise equal in the integer form, to rounding in the float form."""
+    import torch
+    n = 64
+    st = zeldovich_state(n, 10.0, 0.5, seed=9, m_ev=1e-22)
+    lp, _ = cosmo_setup(n, 10.0, 1e-22, precision=precision)
+    fp32 = precision == 0
+    ctx_t = _ctx(pm, lp, gpu)
+    ctx_d = _ctx(pm, lp, gpu)
+    pos, vel = to_device(st, gpu, fp32_positions=fp32)
+    ctx_t.sort(pos, vel)
+    # move every 7th particle by 5.3 cells along y: out of its 4x4x32 tile
+    sel = torch.arange(0, st.npart, 7, device=gpu)
+    if fp32:
+        pos[1, sel] = torch.remainder(pos[1, sel] + 5.3, float(n))
+    else:
+        shift = int(5.3 * 2 ** 32 / n)
+        u = (pos[1, sel].to(torch.int64) & 0xffffffff) + shift
+        u = u & 0xffffffff
+        pos[1, sel] = torch.where(u >= 2 ** 31, u - 2 ** 32, u).to(torch.int32)
+    d_t = torch.empty(n ** 3, dtype=torch.float32, device=gpu)
+    d_d = torch.empty_like(d_t)
+    ctx_t.deposit(pos, d_t)
+    ctx_d.deposit(pos, d_d)
+    torch.cuda.synchronize()
+    if precision == 1:
+        assert np.array_equal(mass_mesh(ctx_t), mass_mesh(ctx_d))
+    else:
+        assert rel_l2(d_t.cpu().numpy(), d_d.cpu().numpy()) < 1e-6
+
+
+def test_sorted_steps_vs_oracle(pm, gpu):
+    """Twenty steps with a sort every 5 steps (tiled deposit and gather)
+    against the oracle, matched through the permuted ids."""
+    import torch
+    n = 64
+    box = 10.0 * n / 256
+    st = zeldovich_state(n, box, 0.01, seed=1, m_ev=1e-22)
+    lp, op = cosmo_setup(n, box, 1e-22)
+    ctx = _ctx(pm, lp, gpu)
+    pos, vel = to_device(st, gpu)
+    ids = torch.arange(st.npart, dtype=torch.int32, device=gpu)
+    times = list(0.01 * np.exp(np.arange(21) * math.log(100.0) / 500))
+    ctx.sort(pos, vel, ids)
+    ctx.step(pos, vel, times[:11])
+    ctx.sort(pos, vel, ids)
+    ctx.step(pos, vel, times[10:], flags=pm.PM_CONTINUE)
+    torch.cuda.synchronize()
+    xo, vo = oracle.run(st.pos, st.vel, op, times)
+    idn = ids.cpu().numpy()
+    xg = positions_cells(pos, n)
+    assert np.max(np.abs(periodic_diff(xg, xo[idn], n))) < 1e-5
+    assert rel_l2(vel.cpu().numpy().T, vo[idn]) < 1e-5
+
+
+def test_step_sort_every_flag(pm, gpu):
+    """PM_SORT_EVERY inside pm_step evolves the same particle set as the
+    unsorted run: order-independent comparisons (density field of the final
+    positions, sums of velocity moments)."""
+    import torch
+    n = 32
+    st = zeldovich_state(n, 10.0, 0.05, seed=2, m_ev=1e-22)
+    lp, _ = cosmo_setup(n, 10.0, 1e-22)
+    times = list(0.05 * np.exp(np.arange(9) * 0.01))
+    c1 = _ctx(pm, lp, gpu)
+    p1, v1 = to_device(st, gpu)
+    c1.step(p1, v1, times)
+    c2 = _ctx(pm, lp, gpu)
+    p2, v2 = to_device(st, gpu)
+    c2.step(p2, v2, times, flags=pm.PM_SORT_EVERY(3))
+    torch.cuda.synchronize()
+    d1 = torch.empty(n ** 3, dtype=torch.float32, device=gpu)
+    d2 = torch.empty_like(d1)
+    c1.deposit(p1, d1)
+    c2.deposit(p2, d2)
+    torch.cuda.synchronize()
+    assert rel_l2(d2.cpu().numpy(), d1.cpu().numpy()) < 1e-6
+    a = v1.cpu().numpy().astype(np.float64)
+    b = v2.cpu().numpy().astype(np.float64)
+    for k in (1, 2):
+        assert abs((b ** k).sum() - (a ** k).sum()) < 1e-6 * np.abs(a ** k).sum()
