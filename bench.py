@@ -106,6 +106,47 @@ def run_gpu(st, n, steps, warmup, a_start, kernel_pass=True, sort_every=10):
     return out
 
 
+def copy_calibration(nbytes=1 << 30, reps=3):
+    """A plain device copy of known size, for scaling HBM byte counters."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    torch.cuda.empty_cache()
+
+
+# rocprofv3 kernel-name prefix of each kernel family in the traffic summary
+TRAFFIC_KERNEL = {"gather_kick_drift": "k_gather_tiled<8, true, true, 1>",
+                  "deposit": "k_deposit_tiled<8, true>", "qpot": "k_qpot<8, true, false>",
+                  "r2c_z": "k_r2c_z<8, 0>", "fft_y": "k_fft_y<8, false>",
+                  "fft_x_green": "k_fft_x_green<8>", "fft_y_inv": "k_fft_y<8, true>",
+                  "c2r_z": "k_c2r_z<8>"}
+
+
+def measured_traffic(kernel: str, n: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None if there is none for this kernel and size or if any kernel source
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"pm_step_{n}_traffic.json")
+    if not os.path.exists(path) or kernel not in TRAFFIC_KERNEL:
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    for f, h in rec.get("source_sha256_16", {}).items():
+        src = os.path.join(ROOT, "paper_1608_00802_amd", "csrc", f)
+        if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != h:
+            return None
+    k = rec["kernels"].get(TRAFFIC_KERNEL[kernel])
+    if k is None:
+        return None
+    return int(k["fetch_bytes"] + k["write_bytes"])
+
+
 def kernel_table(kern, n, npart):
     ab = alg_bytes(n, npart)
     rows = {}
@@ -152,6 +193,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-clustered", action="store_true")
     ap.add_argument("--no-kernel-pass", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--sort-every", type=int, default=10,
                     help="sort particles by tile every k steps inside the timed steps (0: never)")
     args = ap.parse_args()
@@ -160,6 +203,8 @@ def main():
               "(the single-GPU box is the whole measured job)", file=sys.stderr)
         sys.exit(2)
     n = args.n
+    if args.copy_calibration:
+        copy_calibration()
     st = make_state(n, None)
     res = run_gpu(st, n, args.steps, args.warmup, 0.01, kernel_pass=not args.no_kernel_pass,
                   sort_every=args.sort_every)
@@ -197,7 +242,8 @@ def main():
         ach = timed[dom]["alg_GBs"]
         line["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
                             "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                            "traffic": None}
+                            "traffic": measured_traffic(dom, n),
+                            "alg_bytes": timed[dom]["alg_bytes"]}
         ab = alg_bytes(n, res["np"])
         per_step = ("fill_zero", "deposit", "r2c_z", "fft_y", "fft_x_green", "fft_y_inv", "c2r_z",
                     "qpot", "gather_kick_drift")
