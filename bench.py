@@ -49,7 +49,9 @@ def alg_bytes(n: int, npart: int) -> dict:
         "fft_y_inv": 2 * spec,
         "c2r_z": spec + 4 * cells,
         "qpot": 8 * cells,                           # delta in, Q out
-        "gather_kick_drift": 48 * npart + 8 * cells,  # pos+vel in/out, phi and Q once
+        # pos+vel in/out, phi and Q once, and the fused deposit of the drifted
+        # particles (read+write of the int64 mass mesh once)
+        "gather_kick_drift": 48 * npart + 8 * cells + 16 * cells,
         "kick": 36 * npart + 8 * cells,
         "sort_count": 12 * npart + 8 * npart,        # positions in, key and rank out
         "sort_scatter": 8 * npart + 48 * npart,      # key, rank, pos+vel in, copies out
@@ -120,8 +122,8 @@ def copy_calibration(nbytes=1 << 30, reps=3):
 
 
 # rocprofv3 kernel-name prefix of each kernel family in the traffic summary
-TRAFFIC_KERNEL = {"gather_kick_drift": "k_gather_tiled<8, true, true, 1>",
-                  "deposit": "k_deposit_tiled<8, true>", "qpot": "k_qpot<8, true, false>",
+TRAFFIC_KERNEL = {"gather_kick_drift": "k_gather_tiled<8, true, true, 1, true>",
+                  "deposit": "k_deposit_tiled<8, true>", "qpot": "k_qpot_tiled<8, true, false>",
                   "r2c_z": "k_r2c_z<8, 0>", "fft_y": "k_fft_y<8, false>",
                   "fft_x_green": "k_fft_x_green<8>", "fft_y_inv": "k_fft_y<8, true>",
                   "c2r_z": "k_c2r_z<8>"}
@@ -245,7 +247,7 @@ def main():
                             "traffic": measured_traffic(dom, n),
                             "alg_bytes": timed[dom]["alg_bytes"]}
         ab = alg_bytes(n, res["np"])
-        per_step = ("fill_zero", "deposit", "r2c_z", "fft_y", "fft_x_green", "fft_y_inv", "c2r_z",
+        per_step = ("fill_zero", "r2c_z", "fft_y", "fft_x_green", "fft_y_inv", "c2r_z",
                     "qpot", "gather_kick_drift")
         step_bytes = sum(ab[k] for k in per_step)
         line["step_alg_bytes"] = step_bytes

@@ -164,7 +164,7 @@ pm_status pm_force(pm_ctx* ctx, const float* d_phi, const float* d_q,
 pm_status pm_step(pm_ctx* ctx, void* d_pos, float* d_vel, const double* times,
                   int32_t nsteps, int32_t flags);
 
-/* Reorder the particles in place by mesh tile (4 x 4 x 32 cells; counting
+/* Reorder the particles in place by mesh tile (8 x 8 x 32 cells; counting
  * sort, order inside a tile unspecified) and remember the tile ranges.
  * Afterwards the deposit and the gather stage each tile's mesh window in
  * LDS.  Positions and velocities are permuted together; d_ids (int32 [Np],

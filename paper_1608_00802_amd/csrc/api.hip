@@ -60,8 +60,11 @@ struct pm_ctx {
   float* s2;
   double* partials;  // energy partial sums
   double* result;    // reduced energies (device)
-  unsigned* tile_counts;
-  unsigned* tile_start;  // [tiles + 1], valid once sorted
+  unsigned* tile_counts;  // [tiles * kSlices]
+  unsigned* slice_start;  // [tiles * kSlices + 1]
+  unsigned* tile_start;   // [tiles + 1], valid once sorted
+  unsigned* chunk_start;  // [tiles + 1]
+  TileMap tmap;
   unsigned* sort_key;
   unsigned* sort_rank;
   uint32_t* pos_tmp;
@@ -91,8 +94,8 @@ int ilog2_exact(int n) {
 }
 
 struct Layout {
-  size_t mass, delta, phi, q, spec, tw, s2, partials, result, tile_counts, tile_start, sort_key,
-      sort_rank, pos_tmp, vel_tmp, ids_tmp, total;
+  size_t mass, delta, phi, q, spec, tw, s2, partials, result, tile_counts, slice_start,
+      tile_start, chunk_start, sort_key, sort_rank, pos_tmp, vel_tmp, ids_tmp, total;
 };
 
 Layout layout_for(const pm_params& p) {
@@ -118,8 +121,10 @@ Layout layout_for(const pm_params& p) {
   const int logn = ilog2_exact(p.n_mesh);
   const size_t tiles = logn > 0 ? (size_t)tile_count(logn) : 1;
   const size_t np = (size_t)(p.n_part > 0 ? p.n_part : 1);
-  L.tile_counts = take(4 * tiles);
+  L.tile_counts = take(4 * tiles * kSlices);
+  L.slice_start = take(4 * (tiles * kSlices + 1));
   L.tile_start = take(4 * (tiles + 1));
+  L.chunk_start = take(4 * (tiles + 1));
   L.sort_key = take(4 * np);
   L.sort_rank = take(4 * np);
   L.pos_tmp = take(12 * np);
@@ -270,14 +275,14 @@ pm_status run_deposit(pm_ctx* c, const void* pos) {
   return timed(c, kcDeposit, [&] {
     if (c->fixed && c->sorted)
       return launch_deposit_fixed_tiled(static_cast<const uint32_t*>(pos), c->np, c->logn,
-                                        c->tile_start, static_cast<unsigned long long*>(c->mass),
+                                        c->tmap, static_cast<unsigned long long*>(c->mass),
                                         c->stream);
     if (c->fixed)
       return launch_deposit_fixed(static_cast<const uint32_t*>(pos), c->np, c->logn,
                                   static_cast<unsigned long long*>(c->mass), c->stream);
     if (c->sorted)
-      return launch_deposit_f32_tiled(static_cast<const float*>(pos), c->np, c->logn,
-                                      c->tile_start, static_cast<float*>(c->mass), c->stream);
+      return launch_deposit_f32_tiled(static_cast<const float*>(pos), c->np, c->logn, c->tmap,
+                                      static_cast<float*>(c->mass), c->stream);
     return launch_deposit_f32(static_cast<const float*>(pos), c->np, c->logn,
                               static_cast<float*>(c->mass), c->stream);
   });
@@ -309,8 +314,9 @@ pm_status run_qpot(pm_ctx* c, const float* delta, bool use_mass, bool energy) {
 }
 
 // deposit + Poisson + Q at the given positions, all into the workspace
-pm_status run_fields(pm_ctx* c, const void* pos, bool energy) {
-  PM_TRY(run_deposit(c, pos));
+// (deposit = false: the mass mesh already holds them, from the fused push)
+pm_status run_fields(pm_ctx* c, const void* pos, bool energy, bool deposit = true) {
+  if (deposit) PM_TRY(run_deposit(c, pos));
   PM_TRY(run_poisson(c, c->fixed ? kSrcMass64 : kSrcAcc32, c->mass));
   c->have_delta = true;
   c->have_phi = true;
@@ -384,13 +390,18 @@ pm_status pm_init(const pm_params* params, void* d_workspace, size_t bytes, void
   c->partials = reinterpret_cast<double*>(base + L.partials);
   c->result = reinterpret_cast<double*>(base + L.result);
   c->tile_counts = reinterpret_cast<unsigned*>(base + L.tile_counts);
+  c->slice_start = reinterpret_cast<unsigned*>(base + L.slice_start);
   c->tile_start = reinterpret_cast<unsigned*>(base + L.tile_start);
+  c->chunk_start = reinterpret_cast<unsigned*>(base + L.chunk_start);
   c->sort_key = reinterpret_cast<unsigned*>(base + L.sort_key);
   c->sort_rank = reinterpret_cast<unsigned*>(base + L.sort_rank);
   c->pos_tmp = reinterpret_cast<uint32_t*>(base + L.pos_tmp);
   c->vel_tmp = reinterpret_cast<float*>(base + L.vel_tmp);
   c->ids_tmp = reinterpret_cast<int*>(base + L.ids_tmp);
   c->tiles = tile_count(c->logn);
+  c->tmap.start = c->tile_start;
+  c->tmap.chunk_start = c->chunk_start;
+  c->tmap.tiles = c->tiles;
   c->sorted = false;
   c->q_blocks = qpot_blocks(c->logn);
   c->k_blocks = kinetic_blocks(c->np);
@@ -497,11 +508,13 @@ pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int
     gc.fg = (float)(close.g + open.g);
     gc.fq = (float)(close.q + open.q);
     gc.fd_units = drift(c->p, t0, t1) * fdu;
+    // gather + kick + drift, fused with the deposit of the drifted particles
+    PM_TRY(timed(c, kcFill, [&] { return launch_fill_zero(c->mass, 8 * c->ncell, c->stream); }));
     PM_TRY(timed(c, kcGatherKD, [&] {
       return launch_gather(c->fixed, c->has_q, true, c->logn, d_pos, d_vel, c->phi, c->q, c->np,
-                           gc, c->sorted ? c->tile_start : nullptr, c->stream);
+                           gc, c->sorted ? &c->tmap : nullptr, c->mass, c->stream);
     }));
-    PM_TRY(run_fields(c, d_pos, false));
+    PM_TRY(run_fields(c, d_pos, false, false));
     close = kick(c->p, tm, t1);
   }
   GatherConst gc;
@@ -510,7 +523,7 @@ pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int
   gc.fd_units = 0.0;
   PM_TRY(timed(c, kcKick, [&] {
     return launch_gather(c->fixed, c->has_q, false, c->logn, d_pos, d_vel, c->phi, c->q, c->np,
-                         gc, c->sorted ? c->tile_start : nullptr, c->stream);
+                         gc, c->sorted ? &c->tmap : nullptr, nullptr, c->stream);
   }));
   c->fields_at_pos = true;
   return PM_OK;
@@ -518,18 +531,19 @@ pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int
 
 pm_status pm_sort(pm_ctx* c, void* d_pos, float* d_vel, int32_t* d_ids) {
   if (!c || !d_pos || !d_vel) return PM_EINVAL;
-  const size_t cbytes = (4 * (size_t)c->tiles + 15) & ~(size_t)15;
+  const size_t cbytes = (4 * (size_t)c->tiles * kSlices + 15) & ~(size_t)15;
   PM_TRY(timed(c, kcFill, [&] { return launch_fill_zero(c->tile_counts, cbytes, c->stream); }));
   PM_TRY(timed(c, kcSortCount, [&] {
     return launch_sort_count(c->fixed, d_pos, c->np, c->logn, c->tile_counts, c->sort_key,
                              c->sort_rank, c->stream);
   }));
   PM_TRY(timed(c, kcSortScan, [&] {
-    return launch_sort_scan(c->tile_counts, c->tiles, c->tile_start, c->stream);
+    return launch_sort_scan(c->tile_counts, c->tiles, c->slice_start, c->tile_start,
+                            c->chunk_start, c->stream);
   }));
   PM_TRY(timed(c, kcSortScatter, [&] {
     return launch_sort_scatter(d_pos, d_vel, d_ids, c->np, c->sort_key, c->sort_rank,
-                               c->tile_start, c->pos_tmp, c->vel_tmp, c->ids_tmp, c->stream);
+                               c->slice_start, c->pos_tmp, c->vel_tmp, c->ids_tmp, c->stream);
   }));
   PM_TRY(timed(c, kcSortCopy, [&] {
     hipError_t e = hipMemcpyAsync(d_pos, c->pos_tmp, 12 * (size_t)c->np,

@@ -16,6 +16,7 @@
 // last bits), kept as the comparison baseline.
 #include <type_traits>
 
+#include "cic.h"
 #include "internal.h"
 
 namespace fdm {
@@ -34,69 +35,6 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
   if (blocks > 8192) blocks = 8192;
   hipLaunchKernelGGL(k_fill_zero16, dim3((unsigned)blocks), dim3(kBlock), 0, s, (uint4*)p, n16);
   return hipGetLastError();
-}
-
-// Cell index and the eight integer corner weights (2^40 units per particle)
-// of one fixed-point particle.  Corner c = 4 cx + 2 cy + cz.
-template <int LOGN>
-__device__ __forceinline__ void fixed_weights(uint32_t ux, uint32_t uy, uint32_t uz, int& ix,
-                                              int& iy, int& iz, unsigned long long w[8]) {
-  constexpr int B = 32 - LOGN;
-  constexpr unsigned long long ONE = 1ull << B;
-  const double scale = ldexp(1.0, kMassShift - 3 * B);  // 2^(40 - 3B), exact
-  ix = (int)(ux >> B);
-  iy = (int)(uy >> B);
-  iz = (int)(uz >> B);
-  const unsigned long long fx = ux & (ONE - 1), fy = uy & (ONE - 1), fz = uz & (ONE - 1);
-  const unsigned long long wx[2] = {ONE - fx, fx};
-  const unsigned long long wy[2] = {ONE - fy, fy};
-  const unsigned long long wz[2] = {ONE - fz, fz};
-  const int big = ((fx >= (ONE >> 1)) << 2) | ((fy >= (ONE >> 1)) << 1) | (fz >= (ONE >> 1));
-  unsigned long long sum = 0;
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    const unsigned long long wxy = wx[c >> 2] * wy[(c >> 1) & 1];
-    w[c] = (unsigned long long)rint((double)wxy * (double)wz[c & 1] * scale);
-    sum += (c == big) ? 0ull : w[c];
-  }
-  // remainder to the heaviest corner: exactly 2^40 per particle
-#pragma unroll
-  for (int c = 0; c < 8; ++c)
-    if (c == big) w[c] = (1ull << kMassShift) - sum;
-}
-
-// Cell index and trilinear weights of one float particle.
-template <int LOGN>
-__device__ __forceinline__ void float_weights(float x, float y, float z, int& ix, int& iy,
-                                              int& iz, float w[8]) {
-  constexpr int MASK = (1 << LOGN) - 1;
-  const float flx = floorf(x), fly = floorf(y), flz = floorf(z);
-  const float fx = x - flx, fy = y - fly, fz = z - flz;
-  ix = (int)flx & MASK;
-  iy = (int)fly & MASK;
-  iz = (int)flz & MASK;
-  const float wx[2] = {1.0f - fx, fx}, wy[2] = {1.0f - fy, fy}, wz[2] = {1.0f - fz, fz};
-#pragma unroll
-  for (int c = 0; c < 8; ++c) w[c] = wx[c >> 2] * wy[(c >> 1) & 1] * wz[c & 1];
-}
-
-__device__ __forceinline__ void add_global(unsigned long long* p, unsigned long long v) {
-  atomicAdd(p, v);
-}
-__device__ __forceinline__ void add_global(float* p, float v) { unsafeAtomicAdd(p, v); }
-
-template <int LOGN, typename T>
-__device__ __forceinline__ void deposit_global(T* __restrict__ mass, int ix, int iy, int iz,
-                                               const T w[8]) {
-  constexpr int N = 1 << LOGN;
-  constexpr int MASK = N - 1;
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    const int cx = (ix + (c >> 2)) & MASK;
-    const int cy = (iy + ((c >> 1) & 1)) & MASK;
-    const int cz = (iz + (c & 1)) & MASK;
-    if (w[c] != (T)0) add_global(&mass[((size_t)cx * N + cy) * N + cz], w[c]);
-  }
 }
 
 template <int LOGN>
@@ -136,22 +74,22 @@ __global__ void __launch_bounds__(kBlock) k_deposit_f32(const float* __restrict_
 // well sorted the particles are.
 template <int LOGN, bool FIXED>
 __global__ void __launch_bounds__(kBlock) k_deposit_tiled(const void* __restrict__ pos,
-                                                          int64_t np,
-                                                          const unsigned* __restrict__ start,
+                                                          int64_t np, TileMap tm,
                                                           void* __restrict__ mass_v) {
   using T = typename std::conditional<FIXED, unsigned long long, float>::type;
   constexpr int N = 1 << LOGN;
   constexpr int MASK = N - 1;
-  constexpr int TX = 1 << kTileLX, TY = 1 << kTileLY, TZ = 1 << tile_lz(LOGN);
+  constexpr int TX = 1 << tile_lx(LOGN), TY = 1 << tile_ly(LOGN), TZ = 1 << tile_lz(LOGN);
   constexpr int WX = TX + 1, WY = TY + 1, WZ = TZ + 1;
   constexpr int NTY = N / TY, NTZ = N / TZ;
   __shared__ T acc[WX * WY * WZ];
   T* mass = static_cast<T*>(mass_v);
-  const int t = blockIdx.x;
+  int t;
+  unsigned lo, hi;
+  if (!chunk_of(tm, t, lo, hi)) return;
   const int ox = (t / (NTY * NTZ)) * TX, oy = ((t / NTZ) % NTY) * TY, oz = (t % NTZ) * TZ;
   for (int c = threadIdx.x; c < WX * WY * WZ; c += kBlock) acc[c] = (T)0;
   __syncthreads();
-  const unsigned lo = start[t], hi = start[t + 1];
   for (unsigned i = lo + threadIdx.x; i < hi; i += kBlock) {
     int ix, iy, iz;
     T w[8];
@@ -202,21 +140,21 @@ hipError_t launch_deposit_fixed(const uint32_t* pos, int64_t np, int logn,
 }
 
 hipError_t launch_deposit_fixed_tiled(const uint32_t* pos, int64_t np, int logn,
-                                      const unsigned* start, unsigned long long* mass,
+                                      const TileMap& tm, unsigned long long* mass,
                                       hipStream_t s) {
-  const dim3 g((unsigned)tile_count(logn));
+  const dim3 g(tiled_grid(np, tm.tiles));
 #define L_(LN) \
-  hipLaunchKernelGGL((k_deposit_tiled<LN, true>), g, dim3(kBlock), 0, s, pos, np, start, mass)
+  hipLaunchKernelGGL((k_deposit_tiled<LN, true>), g, dim3(kBlock), 0, s, pos, np, tm, mass)
   FDM_LOGN_SWITCH(logn, L_)
 #undef L_
   return hipGetLastError();
 }
 
-hipError_t launch_deposit_f32_tiled(const float* pos, int64_t np, int logn,
-                                    const unsigned* start, float* acc, hipStream_t s) {
-  const dim3 g((unsigned)tile_count(logn));
+hipError_t launch_deposit_f32_tiled(const float* pos, int64_t np, int logn, const TileMap& tm,
+                                    float* acc, hipStream_t s) {
+  const dim3 g(tiled_grid(np, tm.tiles));
 #define L_(LN) \
-  hipLaunchKernelGGL((k_deposit_tiled<LN, false>), g, dim3(kBlock), 0, s, pos, np, start, acc)
+  hipLaunchKernelGGL((k_deposit_tiled<LN, false>), g, dim3(kBlock), 0, s, pos, np, tm, acc)
   FDM_LOGN_SWITCH(logn, L_)
 #undef L_
   return hipGetLastError();

@@ -11,6 +11,14 @@
 //
 // Drift (fixed-point form): u += rint(p * F_d * 2^B) in 64-bit integers, then
 // truncated to 32 bits, which is the periodic wrap done exactly.
+//
+// With DEP the same pass also deposits each drifted particle (step (i) of
+// the next step): into the LDS window of the block's tile when the particle
+// is still inside it, else with direct global atomics; the window is added
+// to the mass mesh at the end of the block.  The caller zeroes the mesh.
+#include <type_traits>
+
+#include "cic.h"
 #include "internal.h"
 
 namespace fdm {
@@ -40,62 +48,47 @@ __device__ __forceinline__ void load_cell(const void* __restrict__ pos, int64_t 
 
 // Interpolated -grad F at one particle.  at(a, b, c) returns F at offsets
 // (a - 1, b - 1, c - 1) from the particle's base cell, a, b, c in 0..3.
+// Central differences at the 8 CIC nodes use the 2x2x2 core and, per axis,
+// the two planes outside it; each axis' extra nodes are consumed as soon as
+// they are read, so only the core stays live.
 template <typename At>
 __device__ __forceinline__ void interp_grad(const float f[3], At&& at, float g[3]) {
-  // fx4[a][b][c]: x offset a (0..3), y offset 1 + b, z offset 1 + c
-  float fx4[4][2][2];
-  // fy2[a][b][c]: x offset 1 + a, y offset 0 (b = 0) or 3 (b = 1), z offset 1 + c
-  float fy2[2][2][2];
-  // fz2[a][b][c]: x offset 1 + a, y offset 1 + b, z offset 0 (c = 0) or 3 (c = 1)
-  float fz2[2][2][2];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int c = 0; c < 2; ++c) fx4[a][b][c] = at(a, 1 + b, 1 + c);
+  float core[2][2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        fy2[a][b][c] = at(1 + a, 3 * b, 1 + c);
-        fz2[a][b][c] = at(1 + a, 1 + b, 3 * c);
-      }
+      for (int c = 0; c < 2; ++c) core[a][b][c] = at(1 + a, 1 + b, 1 + c);
   const float wx[2] = {1.0f - f[0], f[0]};
   const float wy[2] = {1.0f - f[1], f[1]};
   const float wz[2] = {1.0f - f[2], f[2]};
-  auto fyl = [&](int a, int j, int c) -> float {  // x offset 1+a, y offset j, z offset 1+c
-    return j == 0 ? fy2[a][0][c] : (j == 3 ? fy2[a][1][c] : fx4[1 + a][j - 1][c]);
-  };
-  auto fzl = [&](int a, int b, int k) -> float {  // x offset 1+a, y offset 1+b, z offset k
-    return k == 0 ? fz2[a][b][0] : (k == 3 ? fz2[a][b][1] : fx4[1 + a][b][k - 1]);
-  };
-  g[0] = g[1] = g[2] = 0.0f;
+  float gx = 0.0f, gy = 0.0f, gz = 0.0f;
 #pragma unroll
   for (int b = 0; b < 2; ++b)
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-      const float w = wy[b] * wz[c];
-      g[0] += w * (wx[0] * (fx4[2][b][c] - fx4[0][b][c]) + wx[1] * (fx4[3][b][c] - fx4[1][b][c]));
+      // node x offset 0 -> difference F(+1) - F(-1) uses core[1] and the plane at offset -1
+      const float lo = at(0, 1 + b, 1 + c), hi = at(3, 1 + b, 1 + c);
+      gx += wy[b] * wz[c] * (wx[0] * (core[1][b][c] - lo) + wx[1] * (hi - core[0][b][c]));
     }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-      const float w = wx[a] * wz[c];
-      g[1] += w * (wy[0] * (fyl(a, 2, c) - fyl(a, 0, c)) + wy[1] * (fyl(a, 3, c) - fyl(a, 1, c)));
+      const float lo = at(1 + a, 0, 1 + c), hi = at(1 + a, 3, 1 + c);
+      gy += wx[a] * wz[c] * (wy[0] * (core[a][1][c] - lo) + wy[1] * (hi - core[a][0][c]));
     }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      const float w = wx[a] * wy[b];
-      g[2] += w * (wz[0] * (fzl(a, b, 2) - fzl(a, b, 0)) + wz[1] * (fzl(a, b, 3) - fzl(a, b, 1)));
+      const float lo = at(1 + a, 1 + b, 0), hi = at(1 + a, 1 + b, 3);
+      gz += wx[a] * wy[b] * (wz[0] * (core[a][b][1] - lo) + wz[1] * (hi - core[a][b][0]));
     }
-#pragma unroll
-  for (int d = 0; d < 3; ++d) g[d] *= -0.5f;
+  g[0] = -0.5f * gx;
+  g[1] = -0.5f * gy;
+  g[2] = -0.5f * gz;
 }
 
 // Apply the result for particle p: store the force, or kick (and drift).
@@ -103,7 +96,7 @@ template <int LOGN, bool FIXED, int MODE>
 __device__ __forceinline__ void push(void* __restrict__ pos, float* __restrict__ vel,
                                      float* __restrict__ acc, int64_t np, int64_t p,
                                      const float g[3], const uint32_t u[3], const float xf[3],
-                                     double fd_units) {
+                                     double fd_units, uint32_t unew[3], float xnew[3]) {
   constexpr int N = 1 << LOGN;
   if constexpr (MODE == kForce) {
 #pragma unroll
@@ -116,11 +109,13 @@ __device__ __forceinline__ void push(void* __restrict__ pos, float* __restrict__
       if constexpr (MODE == kKickDrift) {
         if constexpr (FIXED) {
           const long long inc = __double2ll_rn((double)v * fd_units);
-          static_cast<uint32_t*>(pos)[d * np + p] = u[d] + (uint32_t)(unsigned long long)inc;
+          unew[d] = u[d] + (uint32_t)(unsigned long long)inc;
+          static_cast<uint32_t*>(pos)[d * np + p] = unew[d];
         } else {
           float x = xf[d] + v * (float)fd_units;
           x = x - (float)N * floorf(x * (1.0f / (float)N));
           if (x >= (float)N) x = 0.0f;
+          xnew[d] = x;
           static_cast<float*>(pos)[d * np + p] = x;
         }
       }
@@ -136,12 +131,24 @@ __device__ __forceinline__ float mesh_f(const float* __restrict__ phi, const flo
   return v;
 }
 
-template <int LOGN, bool FIXED, bool HAS_Q, int MODE>
+// Weights of the drifted particle for the fused deposit.
+template <int LOGN, bool FIXED, typename T>
+__device__ __forceinline__ void new_weights(const uint32_t unew[3], const float xnew[3], int& ix,
+                                            int& iy, int& iz, T w[8]) {
+  if constexpr (FIXED)
+    fixed_weights<LOGN>(unew[0], unew[1], unew[2], ix, iy, iz, w);
+  else
+    float_weights<LOGN>(xnew[0], xnew[1], xnew[2], ix, iy, iz, w);
+}
+
+template <int LOGN, bool FIXED, bool HAS_Q, int MODE, bool DEP>
 __global__ void __launch_bounds__(kBlock) k_gather(void* __restrict__ pos,
                                                    float* __restrict__ vel,
                                                    const float* __restrict__ phi,
                                                    const float* __restrict__ q, int64_t np,
-                                                   GatherConst gc, float* __restrict__ acc) {
+                                                   GatherConst gc, float* __restrict__ acc,
+                                                   void* __restrict__ mass_v) {
+  using T = typename std::conditional<FIXED, unsigned long long, float>::type;
   constexpr int N = 1 << LOGN;
   constexpr int MASK = N - 1;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -156,7 +163,15 @@ __global__ void __launch_bounds__(kBlock) k_gather(void* __restrict__ pos,
                          ((ic[2] + c - 1) & MASK);
       return mesh_f<LOGN, HAS_Q>(phi, q, gc, idx);
     }, g);
-    push<LOGN, FIXED, MODE>(pos, vel, acc, np, p, g, u, xf, gc.fd_units);
+    uint32_t unew[3];
+    float xnew[3];
+    push<LOGN, FIXED, MODE>(pos, vel, acc, np, p, g, u, xf, gc.fd_units, unew, xnew);
+    if constexpr (DEP) {
+      int jx, jy, jz;
+      T w[8];
+      new_weights<LOGN, FIXED>(unew, xnew, jx, jy, jz, w);
+      deposit_global<LOGN>(static_cast<T*>(mass_v), jx, jy, jz, w);
+    }
   }
 }
 
@@ -164,31 +179,37 @@ __global__ void __launch_bounds__(kBlock) k_gather(void* __restrict__ pos,
 // is staged once for the tile's window (cells -1 .. T+1 around the tile) in
 // LDS; particles still inside their tile read their 32 nodes from LDS,
 // particles that left it read the mesh directly.
-template <int LOGN, bool FIXED, bool HAS_Q, int MODE>
-__global__ void __launch_bounds__(kBlock) k_gather_tiled(void* __restrict__ pos,
+template <int LOGN, bool FIXED, bool HAS_Q, int MODE, bool DEP>
+__global__ void __launch_bounds__(kGatherBlock) k_gather_tiled(void* __restrict__ pos,
                                                          float* __restrict__ vel,
                                                          const float* __restrict__ phi,
                                                          const float* __restrict__ q, int64_t np,
-                                                         const unsigned* __restrict__ start,
-                                                         GatherConst gc,
-                                                         float* __restrict__ acc) {
+                                                         TileMap tm, GatherConst gc,
+                                                         float* __restrict__ acc,
+                                                         void* __restrict__ mass_v) {
+  using T = typename std::conditional<FIXED, unsigned long long, float>::type;
   constexpr int N = 1 << LOGN;
   constexpr int MASK = N - 1;
-  constexpr int TX = 1 << kTileLX, TY = 1 << kTileLY, TZ = 1 << tile_lz(LOGN);
+  constexpr int TX = 1 << tile_lx(LOGN), TY = 1 << tile_ly(LOGN), TZ = 1 << tile_lz(LOGN);
   constexpr int WX = TX + 3, WY = TY + 3, WZ = TZ + 3;
   constexpr int NTY = N / TY, NTZ = N / TZ;
+  constexpr int DX = TX + 1, DY = TY + 1, DZ = TZ + 1;
   __shared__ float win[WX * WY * WZ];
-  const int t = blockIdx.x;
+  __shared__ T dacc[DEP ? DX * DY * DZ : 1];
+  int t;
+  unsigned lo, hi;
+  if (!chunk_of(tm, t, lo, hi)) return;
   const int ox = (t / (NTY * NTZ)) * TX, oy = ((t / NTZ) % NTY) * TY, oz = (t % NTZ) * TZ;
-  for (int c = threadIdx.x; c < WX * WY * WZ; c += kBlock) {
+  for (int c = threadIdx.x; c < WX * WY * WZ; c += kGatherBlock) {
     const int lx = c / (WY * WZ), ly = (c / WZ) % WY, lz = c % WZ;
     const size_t idx = ((size_t)((ox - 1 + lx) & MASK) * N + ((oy - 1 + ly) & MASK)) * N +
                        ((oz - 1 + lz) & MASK);
     win[c] = mesh_f<LOGN, HAS_Q>(phi, q, gc, idx);
   }
+  if constexpr (DEP)
+    for (int c = threadIdx.x; c < DX * DY * DZ; c += kGatherBlock) dacc[c] = (T)0;
   __syncthreads();
-  const unsigned lo = start[t], hi = start[t + 1];
-  for (unsigned p = lo + threadIdx.x; p < hi; p += kBlock) {
+  for (unsigned p = lo + threadIdx.x; p < hi; p += kGatherBlock) {
     int ic[3];
     float f[3], xf[3];
     uint32_t u[3];
@@ -206,7 +227,35 @@ __global__ void __launch_bounds__(kBlock) k_gather_tiled(void* __restrict__ pos,
         return mesh_f<LOGN, HAS_Q>(phi, q, gc, idx);
       }, g);
     }
-    push<LOGN, FIXED, MODE>(pos, vel, acc, np, p, g, u, xf, gc.fd_units);
+    uint32_t unew[3];
+    float xnew[3];
+    push<LOGN, FIXED, MODE>(pos, vel, acc, np, p, g, u, xf, gc.fd_units, unew, xnew);
+    if constexpr (DEP) {
+      int jx, jy, jz;
+      T w[8];
+      new_weights<LOGN, FIXED>(unew, xnew, jx, jy, jz, w);
+      const int sx = (jx - ox) & MASK, sy = (jy - oy) & MASK, sz = (jz - oz) & MASK;
+      if (sx < TX && sy < TY && sz < TZ) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+          atomicAdd(&dacc[((sx + (c >> 2)) * DY + sy + ((c >> 1) & 1)) * DZ + sz + (c & 1)], w[c]);
+      } else {
+        deposit_global<LOGN>(static_cast<T*>(mass_v), jx, jy, jz, w);
+      }
+    }
+  }
+  if constexpr (DEP) {
+    __syncthreads();
+    T* mass = static_cast<T*>(mass_v);
+    for (int c = threadIdx.x; c < DX * DY * DZ; c += kGatherBlock) {
+      const T v = dacc[c];
+      if (v != (T)0) {
+        const int lx = c / (DY * DZ), ly = (c / DZ) % DY, lz = c % DZ;
+        const size_t cell = ((size_t)((ox + lx) & MASK) * N + ((oy + ly) & MASK)) * N +
+                            ((oz + lz) & MASK);
+        add_global(&mass[cell], v);
+      }
+    }
   }
 }
 
@@ -217,59 +266,68 @@ static unsigned grid_particles(int64_t np) {
   return (unsigned)b;
 }
 
-template <int LN, int MODE>
+template <int LN, int MODE, bool DEP>
 static void launch_mode_tiled(bool fixed, bool has_q, hipStream_t s, void* pos, float* vel,
-                              const float* phi, const float* q, int64_t np,
-                              const unsigned* start, const GatherConst& gc, float* acc) {
-  const dim3 g((unsigned)tile_count(LN));
+                              const float* phi, const float* q, int64_t np, const TileMap& tm,
+                              const GatherConst& gc, float* acc, void* mass) {
+  const dim3 g(tiled_grid(np, tm.tiles));
   if (fixed && has_q)
-    hipLaunchKernelGGL((k_gather_tiled<LN, true, true, MODE>), g, dim3(kBlock), 0, s, pos, vel,
-                       phi, q, np, start, gc, acc);
+    hipLaunchKernelGGL((k_gather_tiled<LN, true, true, MODE, DEP>), g, dim3(kGatherBlock), 0, s, pos,
+                       vel, phi, q, np, tm, gc, acc, mass);
   else if (fixed)
-    hipLaunchKernelGGL((k_gather_tiled<LN, true, false, MODE>), g, dim3(kBlock), 0, s, pos, vel,
-                       phi, q, np, start, gc, acc);
+    hipLaunchKernelGGL((k_gather_tiled<LN, true, false, MODE, DEP>), g, dim3(kGatherBlock), 0, s, pos,
+                       vel, phi, q, np, tm, gc, acc, mass);
   else if (has_q)
-    hipLaunchKernelGGL((k_gather_tiled<LN, false, true, MODE>), g, dim3(kBlock), 0, s, pos, vel,
-                       phi, q, np, start, gc, acc);
+    hipLaunchKernelGGL((k_gather_tiled<LN, false, true, MODE, DEP>), g, dim3(kGatherBlock), 0, s, pos,
+                       vel, phi, q, np, tm, gc, acc, mass);
   else
-    hipLaunchKernelGGL((k_gather_tiled<LN, false, false, MODE>), g, dim3(kBlock), 0, s, pos, vel,
-                       phi, q, np, start, gc, acc);
+    hipLaunchKernelGGL((k_gather_tiled<LN, false, false, MODE, DEP>), g, dim3(kGatherBlock), 0, s, pos,
+                       vel, phi, q, np, tm, gc, acc, mass);
 }
 
-template <int LN, int MODE>
+template <int LN, int MODE, bool DEP>
 static void launch_mode(bool fixed, bool has_q, dim3 g, hipStream_t s, void* pos, float* vel,
                         const float* phi, const float* q, int64_t np, const GatherConst& gc,
-                        float* acc) {
+                        float* acc, void* mass) {
   if (fixed && has_q)
-    hipLaunchKernelGGL((k_gather<LN, true, true, MODE>), g, dim3(kBlock), 0, s, pos, vel, phi, q,
-                       np, gc, acc);
+    hipLaunchKernelGGL((k_gather<LN, true, true, MODE, DEP>), g, dim3(kBlock), 0, s, pos, vel, phi,
+                       q, np, gc, acc, mass);
   else if (fixed)
-    hipLaunchKernelGGL((k_gather<LN, true, false, MODE>), g, dim3(kBlock), 0, s, pos, vel, phi,
-                       q, np, gc, acc);
+    hipLaunchKernelGGL((k_gather<LN, true, false, MODE, DEP>), g, dim3(kBlock), 0, s, pos, vel,
+                       phi, q, np, gc, acc, mass);
   else if (has_q)
-    hipLaunchKernelGGL((k_gather<LN, false, true, MODE>), g, dim3(kBlock), 0, s, pos, vel, phi,
-                       q, np, gc, acc);
+    hipLaunchKernelGGL((k_gather<LN, false, true, MODE, DEP>), g, dim3(kBlock), 0, s, pos, vel,
+                       phi, q, np, gc, acc, mass);
   else
-    hipLaunchKernelGGL((k_gather<LN, false, false, MODE>), g, dim3(kBlock), 0, s, pos, vel, phi,
-                       q, np, gc, acc);
+    hipLaunchKernelGGL((k_gather<LN, false, false, MODE, DEP>), g, dim3(kBlock), 0, s, pos, vel,
+                       phi, q, np, gc, acc, mass);
 }
 
 hipError_t launch_gather(bool fixed, bool has_q, bool drift, int logn, void* pos, float* vel,
                          const float* phi, const float* q, int64_t np, const GatherConst& gc,
-                         const unsigned* tile_start, hipStream_t s) {
+                         const TileMap* tm, void* deposit_mass, hipStream_t s) {
   const dim3 g(grid_particles(np));
-#define L_(LN)                                                                               \
-  {                                                                                          \
-    if (tile_start && drift)                                                                 \
-      launch_mode_tiled<LN, kKickDrift>(fixed, has_q, s, pos, vel, phi, q, np, tile_start, gc, \
-                                        nullptr);                                            \
-    else if (tile_start)                                                                     \
-      launch_mode_tiled<LN, kKick>(fixed, has_q, s, pos, vel, phi, q, np, tile_start, gc,     \
-                                   nullptr);                                                 \
-    else if (drift)                                                                          \
-      launch_mode<LN, kKickDrift>(fixed, has_q, g, s, pos, vel, phi, q, np, gc, nullptr);     \
-    else                                                                                     \
-      launch_mode<LN, kKick>(fixed, has_q, g, s, pos, vel, phi, q, np, gc, nullptr);          \
+  const bool dep = drift && deposit_mass != nullptr;
+#define L_(LN)                                                                                 \
+  {                                                                                            \
+    if (tm && dep)                                                                             \
+      launch_mode_tiled<LN, kKickDrift, true>(fixed, has_q, s, pos, vel, phi, q, np, *tm, gc,  \
+                                              nullptr, deposit_mass);                          \
+    else if (tm && drift)                                                                      \
+      launch_mode_tiled<LN, kKickDrift, false>(fixed, has_q, s, pos, vel, phi, q, np, *tm, gc, \
+                                               nullptr, nullptr);                              \
+    else if (tm)                                                                               \
+      launch_mode_tiled<LN, kKick, false>(fixed, has_q, s, pos, vel, phi, q, np, *tm, gc,      \
+                                          nullptr, nullptr);                                   \
+    else if (dep)                                                                              \
+      launch_mode<LN, kKickDrift, true>(fixed, has_q, g, s, pos, vel, phi, q, np, gc, nullptr, \
+                                        deposit_mass);                                         \
+    else if (drift)                                                                            \
+      launch_mode<LN, kKickDrift, false>(fixed, has_q, g, s, pos, vel, phi, q, np, gc,         \
+                                         nullptr, nullptr);                                    \
+    else                                                                                       \
+      launch_mode<LN, kKick, false>(fixed, has_q, g, s, pos, vel, phi, q, np, gc, nullptr,     \
+                                    nullptr);                                                  \
   }
   FDM_LOGN_SWITCH(logn, L_)
 #undef L_
@@ -284,9 +342,9 @@ hipError_t launch_force(bool fixed, bool has_q, int logn, const void* pos, const
   gc.fg = fg;
   gc.fq = fq;
   gc.fd_units = 0.0;
-#define L_(LN)                                                                           \
-  launch_mode<LN, kForce>(fixed, has_q, g, s, const_cast<void*>(pos), nullptr, phi, q, np, \
-                          gc, acc)
+#define L_(LN)                                                                            \
+  launch_mode<LN, kForce, false>(fixed, has_q, g, s, const_cast<void*>(pos), nullptr, phi, q, \
+                                 np, gc, acc, nullptr)
   FDM_LOGN_SWITCH(logn, L_)
 #undef L_
   return hipGetLastError();

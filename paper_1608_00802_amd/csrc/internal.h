@@ -21,14 +21,36 @@
 namespace fdm {
 
 constexpr int kBlock = 256;               // threads per block of the streaming kernels
+#ifndef FDM_GATHER_BLOCK
+#define FDM_GATHER_BLOCK 512
+#endif
+constexpr int kGatherBlock = FDM_GATHER_BLOCK;  // threads per block of the tiled gather
 constexpr int kMassShift = 40;            // one particle = 2^40 integer mass units
 
 // Particle tiles of the sort, the tiled deposit and the tiled gather:
 // 2^kTileLX x 2^kTileLY x 2^kTileLZ cells (z clamped to the mesh size).
-constexpr int kTileLX = 2, kTileLY = 2, kTileLZ = 5;
+#ifndef FDM_TILE_LX
+#define FDM_TILE_LX 3
+#endif
+#ifndef FDM_TILE_LY
+#define FDM_TILE_LY 3
+#endif
+#ifndef FDM_TILE_LZ
+#define FDM_TILE_LZ 5
+#endif
+constexpr int kTileLX = FDM_TILE_LX, kTileLY = FDM_TILE_LY, kTileLZ = FDM_TILE_LZ;
+// A tile's particles are processed in chunks of at most kChunk per block, so
+// heavily populated tiles spread over many blocks.
+constexpr int kChunk = 4096;
+// The sort counts each tile in kSlices sub-counters (chosen by block) to
+// spread same-address atomics on densely populated tiles.
+constexpr int kSlices = 16;
+__host__ __device__ constexpr int tile_lx(int logn) { return logn < kTileLX ? logn : kTileLX; }
+__host__ __device__ constexpr int tile_ly(int logn) { return logn < kTileLY ? logn : kTileLY; }
 __host__ __device__ constexpr int tile_lz(int logn) { return logn < kTileLZ ? logn : kTileLZ; }
 __host__ __device__ constexpr int tile_count(int logn) {
-  return (1 << (logn - kTileLX)) * (1 << (logn - kTileLY)) * (1 << (logn - tile_lz(logn)));
+  return (1 << (logn - tile_lx(logn))) * (1 << (logn - tile_ly(logn))) *
+         (1 << (logn - tile_lz(logn)));
 }
 
 // Sources of the forward z-pass.
@@ -67,20 +89,63 @@ hipError_t launch_deposit_fixed(const uint32_t* pos, int64_t np, int logn,
                                 unsigned long long* mass, hipStream_t s);
 hipError_t launch_deposit_f32(const float* pos, int64_t np, int logn, float* acc,
                               hipStream_t s);
-// tiled variants: particles sorted by tile, tile ranges start[0..tiles]
+// Tiled variants.  The particle sort leaves tile ranges and their chunking:
+struct TileMap {
+  const unsigned* start;        // [tiles + 1] first particle of each tile
+  const unsigned* chunk_start;  // [tiles + 1] first chunk of each tile
+  int tiles;
+};
+// upper bound of the number of chunks: every chunk is full except one per tile
+inline unsigned tiled_grid(int64_t np, int tiles) {
+  return (unsigned)(tiles + (np + kChunk - 1) / kChunk);
+}
+// Block b of a tiled launch handles chunk b: tile t with chunk_start[t] <= b <
+// chunk_start[t + 1] and particles [start[t] + j kChunk, ...) of it,
+// j = b - chunk_start[t].  Returns false for blocks beyond the last chunk
+// (the same answer for every thread of the block).
+__device__ __forceinline__ bool chunk_of(const TileMap& tm, int& tile, unsigned& lo,
+                                         unsigned& hi) {
+  __shared__ int s_tile;
+  const unsigned b = blockIdx.x;
+  if (threadIdx.x == 0) {
+    int t = -1;
+    if (b < tm.chunk_start[tm.tiles]) {
+      int l = 0, r = tm.tiles;  // first index with chunk_start > b lies in (l, r]
+      while (r - l > 1) {
+        const int m = (l + r) >> 1;
+        if (tm.chunk_start[m] <= b) l = m; else r = m;
+      }
+      t = l;
+    }
+    s_tile = t;
+  }
+  __syncthreads();
+  tile = s_tile;
+  if (tile < 0) return false;
+  const unsigned j = b - tm.chunk_start[tile];
+  lo = tm.start[tile] + j * (unsigned)kChunk;
+  const unsigned end = tm.start[tile + 1];
+  hi = lo + (unsigned)kChunk < end ? lo + (unsigned)kChunk : end;
+  return true;
+}
+
 hipError_t launch_deposit_fixed_tiled(const uint32_t* pos, int64_t np, int logn,
-                                      const unsigned* start, unsigned long long* mass,
+                                      const TileMap& tm, unsigned long long* mass,
                                       hipStream_t s);
-hipError_t launch_deposit_f32_tiled(const float* pos, int64_t np, int logn,
-                                    const unsigned* start, float* acc, hipStream_t s);
+hipError_t launch_deposit_f32_tiled(const float* pos, int64_t np, int logn, const TileMap& tm,
+                                    float* acc, hipStream_t s);
 
 // ---- sort.hip
+// counts: [tiles * kSlices]; key[i] = tile * kSlices + slice
 hipError_t launch_sort_count(bool fixed, const void* pos, int64_t np, int logn,
                              unsigned* counts, unsigned* key, unsigned* rank, hipStream_t s);
-hipError_t launch_sort_scan(const unsigned* counts, int n, unsigned* start, hipStream_t s);
+// slice_start: [tiles * kSlices + 1]; tile_start, chunk_start: [tiles + 1]
+hipError_t launch_sort_scan(const unsigned* counts, int tiles, unsigned* slice_start,
+                            unsigned* tile_start, unsigned* chunk_start, hipStream_t s);
 hipError_t launch_sort_scatter(const void* pos, const float* vel, const int* ids, int64_t np,
-                               const unsigned* key, const unsigned* rank, const unsigned* start,
-                               uint32_t* pos_out, float* vel_out, int* ids_out, hipStream_t s);
+                               const unsigned* key, const unsigned* rank,
+                               const unsigned* slice_start, uint32_t* pos_out, float* vel_out,
+                               int* ids_out, hipStream_t s);
 
 // ---- fft.hip
 // Forward transform of the density contrast and Poisson solve, written as
@@ -105,7 +170,8 @@ hipError_t launch_reduce(const double* partials, int nblocks, int ncomp, double*
 // ---- gather.hip
 hipError_t launch_gather(bool fixed, bool has_q, bool drift, int logn, void* pos,
                          float* vel, const float* phi, const float* q, int64_t np,
-                         const GatherConst& gc, const unsigned* tile_start, hipStream_t s);
+                         const GatherConst& gc, const TileMap* tm, void* deposit_mass,
+                         hipStream_t s);
 hipError_t launch_force(bool fixed, bool has_q, int logn, const void* pos,
                         const float* phi, const float* q, int64_t np, float fg, float fq,
                         float* acc, hipStream_t s);

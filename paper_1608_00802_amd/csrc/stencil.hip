@@ -98,12 +98,152 @@ __global__ void __launch_bounds__(kBlock) k_qpot(const float* __restrict__ delta
   }
 }
 
-int qpot_blocks(int logn) { return (int)(((size_t)1 << (3 * logn)) / kBlock); }
+// Tiled version (N >= 32): a block owns a QY x QZ column of (y, z) and sweeps
+// QX consecutive x-planes.  Each plane of s-values (with a one-cell y/z halo)
+// is loaded once into LDS; the x-neighbours stay in registers, so delta is
+// read about (QY+2)(QZ+2)/(QY QZ) times instead of once per stencil point.
+constexpr int QY = 8, QZ = 32, QX = 8;
+static_assert(QY * QZ == kBlock, "one cell per thread and plane");
+
+template <bool FIXED>
+__device__ __forceinline__ float s_of(float d, const QConst& qc) {
+  const float r = 1.0f + d;
+  if constexpr (FIXED) return (r >= qc.floor_f) ? d / (1.0f + sqrtf(r)) : qc.s_floor;
+  return sqrtf(r >= qc.floor_f ? r : qc.floor_f);
+}
+
+template <int LOGN, bool FIXED, bool ENERGY>
+__global__ void __launch_bounds__(kBlock) k_qpot_tiled(const float* __restrict__ delta,
+                                                       const long long* __restrict__ mass,
+                                                       const float* __restrict__ phi,
+                                                       float* __restrict__ q, QConst qc,
+                                                       double* __restrict__ partials) {
+  constexpr int N = 1 << LOGN;
+  constexpr int MASK = N - 1;
+  constexpr int PY = QY + 2, PZ = QZ + 2;
+  __shared__ float pl[PY * PZ];
+  const int nby = N / QY, nbz = N / QZ;
+  const int b = (int)blockIdx.x;
+  const int bz = b % nbz, by = (b / nbz) % nby, bx = b / (nbz * nby);
+  const int y0 = by * QY, z0 = bz * QZ, x0 = bx * QX;
+  const int ty = threadIdx.x / QZ, tz = threadIdx.x % QZ;
+  const int y = y0 + ty, z = z0 + tz;
+  auto load_plane = [&](int x) {
+    const size_t base = (size_t)(x & MASK) * N * N;
+    for (int c = threadIdx.x; c < PY * PZ; c += kBlock) {
+      const int ly = c / PZ, lz = c % PZ;
+      const int gy = (y0 - 1 + ly) & MASK, gz = (z0 - 1 + lz) & MASK;
+      pl[c] = s_of<FIXED>(delta[base + (size_t)gy * N + gz], qc);
+    }
+  };
+  auto inplane = [&]() {
+    const int c = (ty + 1) * PZ + tz + 1;
+    return (pl[c - PZ] + pl[c + PZ]) + (pl[c - 1] + pl[c + 1]);
+  };
+  const float sq_floor = sqrtf((float)qc.fp64_below) - 1.0f;  // s below which the FP64 path runs
+  double wsum = 0.0, usum = 0.0;
+  float s_prev = s_of<FIXED>(delta[((size_t)((x0 - 1) & MASK) * N + y) * N + z], qc);
+  load_plane(x0);
+  __syncthreads();
+  float s_cur = pl[(ty + 1) * PZ + tz + 1];
+  float in_cur = inplane();
+  float sy_cur = pl[(ty + 2) * PZ + tz + 1], sz_cur = pl[(ty + 1) * PZ + tz + 2];
+  __syncthreads();
+  for (int x = x0; x < x0 + QX; ++x) {
+    load_plane(x + 1);
+    __syncthreads();
+    const float s_next = pl[(ty + 1) * PZ + tz + 1];
+    const float in_next = inplane();
+    const float sy_next = pl[(ty + 2) * PZ + tz + 1], sz_next = pl[(ty + 1) * PZ + tz + 2];
+    __syncthreads();
+    const size_t i = ((size_t)x * N + y) * N + z;
+    const float lap = ((s_prev + s_next) + in_cur) - 6.0f * s_cur;
+    float qv;
+    if constexpr (FIXED) {
+      qv = qc.coef * lap / (1.0f + s_cur);
+      if (qc.fp64_below > 0.0 && s_cur < sq_floor + 1e-6f) {
+        // near-empty cell: sqrt(R) and Q in FP64 from the exact integer mass
+        auto sd = [&](int xx, int yy, int zz) {
+          const size_t j = ((size_t)(xx & MASK) * N + (yy & MASK)) * N + (zz & MASK);
+          double r = (double)mass[j] * qc.inv_mbar;
+          r = r > qc.floor_d ? r : qc.floor_d;
+          return sqrt(r);
+        };
+        const double c0 = sd(x, y, z);
+        if (c0 * c0 < qc.fp64_below) {
+          const double lapd = ((sd(x + 1, y, z) + sd(x - 1, y, z)) +
+                               (sd(x, y + 1, z) + sd(x, y - 1, z)) +
+                               (sd(x, y, z + 1) + sd(x, y, z - 1))) - 6.0 * c0;
+          qv = (float)(qc.coef_d * lapd / c0);
+        }
+      }
+    } else {
+      qv = qc.coef * lap / s_cur;
+    }
+    q[i] = qv;
+    if constexpr (ENERGY) {
+      wsum += (double)delta[i] * (double)phi[i];
+      const double e0 = (double)(s_next - s_cur), e1 = (double)(sy_cur - s_cur),
+                   e2 = (double)(sz_cur - s_cur);
+      usum += e0 * e0 + e1 * e1 + e2 * e2;
+    }
+    s_prev = s_cur;
+    s_cur = s_next;
+    in_cur = in_next;
+    sy_cur = sy_next;
+    sz_cur = sz_next;
+  }
+  if constexpr (ENERGY) {
+    __shared__ double red[kBlock / 64];
+    const double ws = block_sum(wsum, red);
+    const double us = block_sum(usum, red);
+    if (threadIdx.x == 0) {
+      partials[2 * (size_t)blockIdx.x] = ws;
+      partials[2 * (size_t)blockIdx.x + 1] = us;
+    }
+  }
+}
+
+int qpot_blocks(int logn) {
+#ifndef FDM_QPOT_SIMPLE
+  if (logn >= 5) return (int)(((size_t)1 << (3 * logn)) / ((size_t)QY * QZ * QX));
+#endif
+  return (int)(((size_t)1 << (3 * logn)) / kBlock);
+}
 
 hipError_t launch_qpot(int logn, bool fixed, bool energy, const float* delta,
                        const long long* mass, const float* phi, float* q, const QConst& qc,
                        double* partials, hipStream_t s) {
   const dim3 g((unsigned)qpot_blocks(logn));
+#ifndef FDM_QPOT_SIMPLE
+  if (logn >= 5) {
+#define T_(LN)                                                                               \
+  {                                                                                          \
+    if (fixed && energy)                                                                     \
+      hipLaunchKernelGGL((k_qpot_tiled<LN, true, true>), g, dim3(kBlock), 0, s, delta, mass,  \
+                         phi, q, qc, partials);                                              \
+    else if (fixed)                                                                          \
+      hipLaunchKernelGGL((k_qpot_tiled<LN, true, false>), g, dim3(kBlock), 0, s, delta, mass, \
+                         phi, q, qc, partials);                                              \
+    else if (energy)                                                                         \
+      hipLaunchKernelGGL((k_qpot_tiled<LN, false, true>), g, dim3(kBlock), 0, s, delta, mass, \
+                         phi, q, qc, partials);                                              \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_qpot_tiled<LN, false, false>), g, dim3(kBlock), 0, s, delta,     \
+                         mass, phi, q, qc, partials);                                        \
+  }
+    switch (logn) {
+      case 5: T_(5); break;
+      case 6: T_(6); break;
+      case 7: T_(7); break;
+      case 8: T_(8); break;
+      case 9: T_(9); break;
+      default: return hipErrorInvalidValue;
+    }
+#undef T_
+    return hipGetLastError();
+  }
+#endif
 #define L_(LN)                                                                            \
   {                                                                                       \
     if (fixed && energy)                                                                  \

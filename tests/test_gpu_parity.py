@@ -375,7 +375,7 @@ def test_sort_is_permutation_by_tile(pm, gpu):
     assert np.array_equal(pos.cpu().numpy(), st.pos_fixed.view(np.int32)[:, idn])
     assert np.array_equal(vel.cpu().numpy(), st.vel32[:, idn])
     cell = pos.cpu().numpy().view(np.uint32) >> (32 - 6)
-    key = ((cell[0] >> 2) * (n // 4) + (cell[1] >> 2)) * (n // 32) + (cell[2] >> 5)
+    key = ((cell[0] >> 3) * (n // 8) + (cell[1] >> 3)) * (n // 32) + (cell[2] >> 5)
     assert np.all(np.diff(key.astype(np.int64)) >= 0)
 
 
@@ -393,12 +393,12 @@ def test_tiled_deposit_equals_direct(pm, gpu, precision):
     ctx_d = _ctx(pm, lp, gpu)
     pos, vel = to_device(st, gpu, fp32_positions=fp32)
     ctx_t.sort(pos, vel)
-    # move every 7th particle by 5.3 cells along y: out of its 4x4x32 tile
+    # move every 7th particle by 9.3 cells along y: out of its 8x8x32 tile
     sel = torch.arange(0, st.npart, 7, device=gpu)
     if fp32:
-        pos[1, sel] = torch.remainder(pos[1, sel] + 5.3, float(n))
+        pos[1, sel] = torch.remainder(pos[1, sel] + 9.3, float(n))
     else:
-        shift = int(5.3 * 2 ** 32 / n)
+        shift = int(9.3 * 2 ** 32 / n)
         u = (pos[1, sel].to(torch.int64) & 0xffffffff) + shift
         u = u & 0xffffffff
         pos[1, sel] = torch.where(u >= 2 ** 31, u - 2 ** 32, u).to(torch.int32)
