@@ -196,6 +196,62 @@ typedef struct {
 pm_status pm_timing_enable(pm_ctx* ctx, int32_t on);
 pm_status pm_timing_read(pm_ctx* ctx, pm_kernel_time* out, int32_t max, int32_t* count);
 
+/* ---------------------------------------------------------------------
+ * Batched runs (serving many independent boxes of one mesh size).
+ *
+ * A batch holds `slots` independent runs that share n_mesh, n_part,
+ * precision, cosmology (or four_pi_G_rhobar) and floors; each slot has its
+ * own box size and hbar/m.  Every kernel of a step is launched once for all
+ * active slots (the launch grid's second dimension enumerates them), so a
+ * step of B small boxes costs one set of launches instead of B.
+ *
+ * Memory: the caller passes one workspace of pm_batch_workspace_bytes bytes;
+ * particle arrays of all slots are contiguous: positions [slots][3][Np]
+ * (uint32 or float), velocities [slots][3][Np] float.  Slot s of the
+ * workspace has the layout of a single context, so bytes [0, 8 N^3) of slot
+ * s hold its mass mesh; slot s starts at pm_batch_slot_offset(batch, s).
+ * ------------------------------------------------------------------- */
+typedef struct pm_batch pm_batch;
+
+typedef struct {
+  double box;           /* side length of this run, caller's length unit */
+  double hbar_over_m;   /* hbar/m of this run (length^2/time), >= 0 */
+} pm_slot_params;
+
+/* Largest number of steps one pm_batch_step call may take. */
+#define PM_BATCH_MAX_STEPS 256
+
+/* Workspace of a batch: params as for pm_workspace_bytes (box and
+ * hbar_over_m are ignored: they are per slot), slots >= 1. */
+pm_status pm_batch_workspace_bytes(const pm_params* params, int32_t slots, size_t* bytes);
+
+/* Create a batch on a caller-owned workspace (256-byte aligned) and stream.
+ * All slots start with box = params->box and hbar_over_m =
+ * params->hbar_over_m. */
+pm_status pm_batch_init(const pm_params* params, int32_t slots, void* d_workspace, size_t bytes,
+                        void* hip_stream, pm_batch** out);
+
+/* Byte offset of slot s's region inside the batch workspace. */
+pm_status pm_batch_slot_offset(const pm_batch* batch, int32_t slot, size_t* offset);
+
+/* Set the box size and hbar/m of one slot (host only; takes effect at the
+ * next pm_batch_step that lists the slot).  Marks the slot's fields stale. */
+pm_status pm_batch_set_slot(pm_batch* batch, int32_t slot, const pm_slot_params* sp);
+
+/* Advance the listed slots (host array slots[0..nactive), distinct, in
+ * range) by nsteps kick-drift-kick steps each, slot slots[i] along its own
+ * schedule times[i * (nsteps + 1) .. i * (nsteps + 1) + nsteps] (host array,
+ * strictly increasing; scale factors in a comoving batch).  State in and out
+ * is synchronised, as for pm_step.  flags: PM_CONTINUE (every listed slot's
+ * fields are those of its positions, left by the previous pm_batch_step) and
+ * PM_SORT_EVERY(k).  1 <= nsteps <= PM_BATCH_MAX_STEPS. */
+pm_status pm_batch_step(pm_batch* batch, void* d_pos, float* d_vel, int32_t nactive,
+                        const int32_t* slots, const double* times, int32_t nsteps,
+                        int32_t flags);
+
+/* Free the host-side batch object. */
+pm_status pm_batch_destroy(pm_batch* batch);
+
 /* Free the host-side context (no device memory is owned). */
 pm_status pm_destroy(pm_ctx* ctx);
 

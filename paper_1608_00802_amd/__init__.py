@@ -10,11 +10,13 @@ from ._lib import (  # noqa: F401
     PM_FIXED32,
     PM_FP32,
     PM_SORT_EVERY,
+    PMBatch,
     PMContext,
     PMError,
     PMParams,
     load_library,
     make_params,
+    pm_batch_step,
     pm_deposit,
     pm_destroy,
     pm_energy,

@@ -26,7 +26,10 @@ def PM_SORT_EVERY(k: int) -> int:
 
 EXPORTED = ("pm_workspace_bytes", "pm_init", "pm_deposit", "pm_poisson", "pm_qpot",
             "pm_force", "pm_step", "pm_sort", "pm_energy", "pm_timing_enable", "pm_timing_read",
-            "pm_destroy", "pm_strerror")
+            "pm_batch_workspace_bytes", "pm_batch_init", "pm_batch_slot_offset",
+            "pm_batch_set_slot", "pm_batch_step", "pm_batch_destroy", "pm_destroy",
+            "pm_strerror")
+PM_BATCH_MAX_STEPS = 256
 
 
 class PMParams(ctypes.Structure):
@@ -53,6 +56,10 @@ class PMEnergies(ctypes.Structure):
 
 class PMKernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", c_int64), ("total_ms", c_double)]
+
+
+class PMSlotParams(ctypes.Structure):
+    _fields_ = [("box", c_double), ("hbar_over_m", c_double)]
 
 
 class PMError(RuntimeError):
@@ -86,6 +93,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "pm_energy": ([c_void_p, c_void_p, c_void_p, c_double, P(PMEnergies)], c_int32),
         "pm_timing_enable": ([c_void_p, c_int32], c_int32),
         "pm_timing_read": ([c_void_p, P(PMKernelTime), c_int32, P(c_int32)], c_int32),
+        "pm_batch_workspace_bytes": ([P(PMParams), c_int32, P(c_size_t)], c_int32),
+        "pm_batch_init": ([P(PMParams), c_int32, c_void_p, c_size_t, c_void_p, P(c_void_p)],
+                          c_int32),
+        "pm_batch_slot_offset": ([c_void_p, c_int32, P(c_size_t)], c_int32),
+        "pm_batch_set_slot": ([c_void_p, c_int32, P(PMSlotParams)], c_int32),
+        "pm_batch_step": ([c_void_p, c_void_p, c_void_p, c_int32, P(c_int32), P(c_double),
+                           c_int32, c_int32], c_int32),
+        "pm_batch_destroy": ([c_void_p], c_int32),
         "pm_destroy": ([c_void_p], c_int32),
         "pm_strerror": ([c_int32], ctypes.c_char_p),
     }
@@ -285,6 +300,113 @@ class PMContext:
         if getattr(self, "ctx", None):
             pm_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ batched runs
+
+def pm_batch_workspace_bytes(params: PMParams, slots: int) -> int:
+    n = c_size_t(0)
+    _check(load_library().pm_batch_workspace_bytes(byref(params), int(slots), byref(n)),
+           "pm_batch_workspace_bytes")
+    return n.value
+
+
+def pm_batch_init(params: PMParams, slots: int, workspace_ptr: int, nbytes: int,
+                  stream_ptr: int) -> int:
+    out = c_void_p(None)
+    _check(load_library().pm_batch_init(byref(params), int(slots), c_void_p(workspace_ptr), nbytes,
+                                        c_void_p(stream_ptr), byref(out)), "pm_batch_init")
+    return out.value
+
+
+def pm_batch_slot_offset(batch: int, slot: int) -> int:
+    n = c_size_t(0)
+    _check(load_library().pm_batch_slot_offset(c_void_p(batch), int(slot), byref(n)),
+           "pm_batch_slot_offset")
+    return n.value
+
+
+def pm_batch_set_slot(batch: int, slot: int, box: float, hbar_over_m: float) -> None:
+    sp = PMSlotParams(float(box), float(hbar_over_m))
+    _check(load_library().pm_batch_set_slot(c_void_p(batch), int(slot), byref(sp)),
+           "pm_batch_set_slot")
+
+
+def pm_batch_step(batch: int, pos_ptr: int, vel_ptr: int, slots, times, flags: int = 0) -> None:
+    """slots: list of slot indices; times: one schedule (nsteps + 1 values) per slot."""
+    ns = len(slots)
+    nsteps = len(times[0]) - 1
+    if any(len(t) != nsteps + 1 for t in times) or len(times) != ns:
+        raise ValueError("times: one schedule of equal length per listed slot")
+    sl = (c_int32 * ns)(*[int(s) for s in slots])
+    flat = [float(v) for t in times for v in t]
+    tt = (c_double * len(flat))(*flat)
+    _check(load_library().pm_batch_step(c_void_p(batch), c_void_p(pos_ptr), c_void_p(vel_ptr),
+                                        ns, sl, tt, nsteps, int(flags)), "pm_batch_step")
+
+
+def pm_batch_destroy(batch: int) -> None:
+    _check(load_library().pm_batch_destroy(c_void_p(batch)), "pm_batch_destroy")
+
+
+class PMBatch:
+    """Independent runs of one mesh size stepped together (torch-owned memory).
+
+    Owns the workspace and the particle arrays pos [slots, 3, Np] and
+    vel [slots, 3, Np]; load() copies a run into a slot, fetch() returns
+    copies of a slot's state.
+    """
+
+    def __init__(self, params: PMParams, slots: int, device=None, stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device if device is not None else "cuda:0")
+        self.params = params
+        self.slots = int(slots)
+        self.n = params.n_mesh
+        self.np = params.n_part
+        self.fixed = params.precision == PM_FIXED32
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.nbytes = pm_batch_workspace_bytes(params, slots)
+        pdt = torch.int32 if self.fixed else torch.float32
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+            self.pos = torch.zeros((self.slots, 3, self.np), dtype=pdt, device=self.device)
+            self.vel = torch.zeros((self.slots, 3, self.np), dtype=torch.float32,
+                                   device=self.device)
+            self.batch = pm_batch_init(params, slots, self.workspace.data_ptr(), self.nbytes,
+                                       self.stream.cuda_stream)
+
+    def load(self, slot: int, pos, vel, box: float, hbar_over_m: float):
+        """Copy a run's state (tensors [3, Np], any device) into a slot, on the batch stream."""
+        torch = self.torch
+        want = torch.int32 if self.fixed else torch.float32
+        if tuple(pos.shape) != (3, self.np) or tuple(vel.shape) != (3, self.np) \
+                or pos.dtype != want or vel.dtype != torch.float32:
+            raise ValueError(f"load: need pos {want} and vel float32 of shape [3, {self.np}]")
+        with torch.cuda.stream(self.stream):
+            self.pos[slot].copy_(pos, non_blocking=True)
+            self.vel[slot].copy_(vel, non_blocking=True)
+        pm_batch_set_slot(self.batch, slot, box, hbar_over_m)
+
+    def step(self, slots, times, flags: int = 0):
+        pm_batch_step(self.batch, self.pos.data_ptr(), self.vel.data_ptr(), slots, times, flags)
+
+    def mass_mesh(self, slot: int):
+        off = pm_batch_slot_offset(self.batch, slot)
+        n3 = self.n ** 3
+        return self.workspace[off: off + 8 * n3].view(self.torch.int64)
+
+    def close(self):
+        if getattr(self, "batch", None):
+            pm_batch_destroy(self.batch)
+            self.batch = None
 
     def __del__(self):
         try:

@@ -81,6 +81,19 @@ struct pm_ctx {
   Timer timer;
 };
 
+
+struct pm_batch {
+  pm_ctx base;                 // layout and constants of slot 0
+  int slots;
+  size_t slot_stride;          // bytes between slot regions
+  size_t header;               // bytes before slot 0
+  char* ws;                    // workspace start
+  int* d_slots;                // device list of active slots
+  SlotConst* d_consts;         // device [(max steps + 1) * slots]
+  std::vector<double> box, hm;  // per slot, hm in cells^2/time
+  std::vector<char> fields_ok, sorted;
+};
+
 namespace {
 
 constexpr size_t kAlign = 256;
@@ -330,35 +343,22 @@ pm_status copy_out(pm_ctx* c, float* dst, const float* src) {
   return dev(hipMemcpyAsync(dst, src, 4 * c->ncell, hipMemcpyDeviceToDevice, c->stream));
 }
 
-}  // namespace
-
-extern "C" {
-
-pm_status pm_sort(pm_ctx* c, void* d_pos, float* d_vel, int32_t* d_ids);
-
-pm_status pm_workspace_bytes(const pm_params* params, size_t* bytes) {
-  if (!bytes) return PM_EINVAL;
-  PM_TRY(check_params(params));
-  *bytes = layout_for(*params).total;
-  return PM_OK;
+size_t batch_header(int slots) {
+  return align_up(4 * (size_t)slots) + align_up(sizeof(SlotConst) * (PM_BATCH_MAX_STEPS + 1) *
+                                                (size_t)slots);
 }
 
-pm_status pm_init(const pm_params* params, void* d_workspace, size_t bytes, void* hip_stream,
-                  pm_ctx** out) {
-  if (!out || !d_workspace) return PM_EINVAL;
-  PM_TRY(check_params(params));
-  if (((uintptr_t)d_workspace) % kAlign != 0) return PM_EINVAL;
+// Fill a context for the workspace region at base (layout_for(*params)),
+// upload its constant tables.  params are already checked.
+pm_status ctx_setup(pm_ctx* c, const pm_params* params, char* base, hipStream_t stream) {
   const Layout L = layout_for(*params);
-  if (bytes < L.total) return PM_ENOMEM;
-  pm_ctx* c = new (std::nothrow) pm_ctx();
-  if (!c) return PM_ENOMEM;
   c->p = *params;
   c->N = params->n_mesh;
   c->logn = ilog2_exact(c->N);
   c->B = 32 - c->logn;
   c->np = params->n_part;
   c->ncell = (size_t)c->N * c->N * c->N;
-  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->stream = stream;
   c->fixed = params->precision == PM_FIXED32;
   const double dx = params->box / c->N;
   c->hm = params->hbar_over_m / (dx * dx);
@@ -379,7 +379,6 @@ pm_status pm_init(const pm_params* params, void* d_workspace, size_t bytes, void
   qc.fp64_below = c->fixed ? params->rho_fp64_below : -1.0;
   qc.mbar = mbar;
   qc.inv_mbar = mbar ? 1.0 / (double)mbar : 0.0;
-  char* base = static_cast<char*>(d_workspace);
   c->mass = base + L.mass;
   c->delta = reinterpret_cast<float*>(base + L.delta);
   c->phi = reinterpret_cast<float*>(base + L.phi);
@@ -419,9 +418,35 @@ pm_status pm_init(const pm_params* params, void* d_workspace, size_t bytes, void
     e = hipMemcpyAsync(c->s2, s2.data(), 4 * c->N, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // host vectors die here
   if (e == hipSuccess && !c->has_q) e = launch_fill_zero(c->q, 4 * c->ncell, c->stream);
-  if (e != hipSuccess) {
+  return e == hipSuccess ? PM_OK : PM_EDEVICE;
+}
+
+}  // namespace
+
+extern "C" {
+
+pm_status pm_sort(pm_ctx* c, void* d_pos, float* d_vel, int32_t* d_ids);
+
+pm_status pm_workspace_bytes(const pm_params* params, size_t* bytes) {
+  if (!bytes) return PM_EINVAL;
+  PM_TRY(check_params(params));
+  *bytes = layout_for(*params).total;
+  return PM_OK;
+}
+
+pm_status pm_init(const pm_params* params, void* d_workspace, size_t bytes, void* hip_stream,
+                  pm_ctx** out) {
+  if (!out || !d_workspace) return PM_EINVAL;
+  PM_TRY(check_params(params));
+  if (((uintptr_t)d_workspace) % kAlign != 0) return PM_EINVAL;
+  if (bytes < layout_for(*params).total) return PM_ENOMEM;
+  pm_ctx* c = new (std::nothrow) pm_ctx();
+  if (!c) return PM_ENOMEM;
+  const pm_status st = ctx_setup(c, params, static_cast<char*>(d_workspace),
+                                 static_cast<hipStream_t>(hip_stream));
+  if (st != PM_OK) {
     delete c;
-    return PM_EDEVICE;
+    return st;
   }
   *out = c;
   return PM_OK;
@@ -628,6 +653,200 @@ pm_status pm_timing_read(pm_ctx* c, pm_kernel_time* out, int32_t max, int32_t* c
     ++n;
   }
   *count = n;
+  return PM_OK;
+}
+
+pm_status pm_batch_workspace_bytes(const pm_params* params, int32_t slots, size_t* bytes) {
+  if (!bytes || slots < 1) return PM_EINVAL;
+  PM_TRY(check_params(params));
+  *bytes = batch_header(slots) + (size_t)slots * layout_for(*params).total;
+  return PM_OK;
+}
+
+pm_status pm_batch_init(const pm_params* params, int32_t slots, void* d_workspace, size_t bytes,
+                        void* hip_stream, pm_batch** out) {
+  if (!out || !d_workspace || slots < 1) return PM_EINVAL;
+  PM_TRY(check_params(params));
+  if (((uintptr_t)d_workspace) % kAlign != 0) return PM_EINVAL;
+  const size_t stride = layout_for(*params).total;
+  const size_t header = batch_header(slots);
+  if (bytes < header + (size_t)slots * stride) return PM_ENOMEM;
+  pm_batch* b = new (std::nothrow) pm_batch();
+  if (!b) return PM_ENOMEM;
+  b->slots = slots;
+  b->slot_stride = stride;
+  b->header = header;
+  b->ws = static_cast<char*>(d_workspace);
+  b->d_slots = reinterpret_cast<int*>(b->ws);
+  b->d_consts = reinterpret_cast<SlotConst*>(b->ws + align_up(4 * (size_t)slots));
+  const pm_status st = ctx_setup(&b->base, params, b->ws + header,
+                                 static_cast<hipStream_t>(hip_stream));
+  if (st != PM_OK) {
+    delete b;
+    return st;
+  }
+  b->box.assign(slots, params->box);
+  b->hm.assign(slots, b->base.hm);
+  b->fields_ok.assign(slots, 0);
+  b->sorted.assign(slots, 0);
+  *out = b;
+  return PM_OK;
+}
+
+pm_status pm_batch_slot_offset(const pm_batch* b, int32_t slot, size_t* offset) {
+  if (!b || !offset || slot < 0 || slot >= b->slots) return PM_EINVAL;
+  *offset = b->header + (size_t)slot * b->slot_stride;
+  return PM_OK;
+}
+
+pm_status pm_batch_set_slot(pm_batch* b, int32_t slot, const pm_slot_params* sp) {
+  if (!b || !sp || slot < 0 || slot >= b->slots) return PM_EINVAL;
+  if (!(sp->box > 0.0) || !isfinite(sp->box)) return PM_EINVAL;
+  if (!(sp->hbar_over_m >= 0.0) || !isfinite(sp->hbar_over_m)) return PM_EINVAL;
+  const double dx = sp->box / b->base.N;
+  b->box[slot] = sp->box;
+  b->hm[slot] = sp->hbar_over_m / (dx * dx);
+  b->fields_ok[slot] = 0;
+  return PM_OK;
+}
+
+pm_status pm_batch_step(pm_batch* b, void* d_pos, float* d_vel, int32_t nactive,
+                        const int32_t* slots, const double* times, int32_t nsteps,
+                        int32_t flags) {
+  if (!b || !d_pos || !d_vel || !slots || !times) return PM_EINVAL;
+  if (nactive < 1 || nactive > b->slots) return PM_EINVAL;
+  if (nsteps < 1 || nsteps > PM_BATCH_MAX_STEPS) return PM_EINVAL;
+  if (flags & ~(PM_CONTINUE | PM_SORT_EVERY(0xffff))) return PM_EINVAL;
+  pm_ctx* c = &b->base;
+  std::vector<char> seen(b->slots, 0);
+  bool all_sorted = true, all_fields = true;
+  for (int i = 0; i < nactive; ++i) {
+    const int s = slots[i];
+    if (s < 0 || s >= b->slots || seen[s]) return PM_EINVAL;
+    seen[s] = 1;
+    all_sorted = all_sorted && b->sorted[s];
+    all_fields = all_fields && b->fields_ok[s];
+    const double* t = times + (size_t)i * (nsteps + 1);
+    for (int k = 0; k <= nsteps; ++k) {
+      if (!isfinite(t[k])) return PM_EINVAL;
+      if (c->p.comoving && !(t[k] > 0.0)) return PM_EINVAL;
+      if (k > 0 && !(t[k] > t[k - 1])) return PM_EINVAL;
+    }
+  }
+  if ((flags & PM_CONTINUE) && !all_fields) return PM_ESTATE;
+  const int sort_every = (flags >> 8) & 0xffff;
+  // per-step, per-slot constants: row k < nsteps is the merged kick before
+  // drift k, row nsteps the closing half-kick
+  const double fdu = c->fixed ? ldexp(1.0, c->B) : 1.0;
+  std::vector<SlotConst> tab((size_t)(nsteps + 1) * nactive);
+  for (int i = 0; i < nactive; ++i) {
+    const int s = slots[i];
+    const double* t = times + (size_t)i * (nsteps + 1);
+    const double qd = -0.5 * b->hm[s] * b->hm[s];
+    Kick close = {0.0, 0.0};
+    for (int k = 0; k <= nsteps; ++k) {
+      SlotConst& e = tab[(size_t)k * nactive + i];
+      e.qcoef = (float)qd;
+      e.qcoef_d = qd;
+      e.pad = 0.0f;
+      if (k < nsteps) {
+        const double tm = midpoint(c->p, t[k], t[k + 1]);
+        const Kick open = kick(c->p, t[k], tm);
+        e.fg = (float)(close.g + open.g);
+        e.fq = (float)(close.q + open.q);
+        e.fd_units = drift(c->p, t[k], t[k + 1]) * fdu;
+        close = kick(c->p, tm, t[k + 1]);
+      } else {
+        e.fg = (float)close.g;
+        e.fq = (float)close.q;
+        e.fd_units = 0.0;
+      }
+    }
+  }
+  PM_TRY(dev(hipMemcpyAsync(b->d_slots, slots, 4 * (size_t)nactive, hipMemcpyHostToDevice,
+                            c->stream)));
+  PM_TRY(dev(hipMemcpyAsync(b->d_consts, tab.data(), sizeof(SlotConst) * tab.size(),
+                            hipMemcpyHostToDevice, c->stream)));
+  Batch bt;
+  bt.slots = b->d_slots;
+  bt.ws_stride = (long long)b->slot_stride;
+  bt.part_stride = 12ll * c->np;
+  bt.count = (unsigned)nactive;
+  auto row = [&](int k) {
+    Batch r = bt;
+    r.consts = b->d_consts + (size_t)k * nactive;
+    return r;
+  };
+  bool sorted = all_sorted;
+  const float gscale = (float)(-c->S * 2.0 / ((double)c->N * c->N * c->N));
+  auto fields = [&](const Batch& bq) -> pm_status {
+    PM_TRY(dev(launch_r2c_z(c->logn, c->fixed ? kSrcMass64 : kSrcAcc32, c->mass, c->delta,
+                            c->spec, c->tw, c->conv, c->stream, bt)));
+    PM_TRY(dev(launch_fft_y(c->logn, c->spec, c->tw, false, c->stream, bt)));
+    PM_TRY(dev(launch_fft_x_green(c->logn, c->spec, c->tw, c->s2, gscale, c->stream, bt)));
+    PM_TRY(dev(launch_fft_y(c->logn, c->spec, c->tw, true, c->stream, bt)));
+    PM_TRY(dev(launch_c2r_z(c->logn, c->spec, c->tw, c->phi, c->stream, bt)));
+    return dev(launch_qpot(c->logn, c->fixed, false, c->delta,
+                           static_cast<const long long*>(c->mass), c->phi, c->q, c->qc,
+                           c->partials, c->stream, bq));
+  };
+  auto sort_all = [&]() -> pm_status {
+    const size_t cbytes = (4 * (size_t)c->tiles * kSlices + 15) & ~(size_t)15;
+    PM_TRY(dev(launch_fill_zero(c->tile_counts, cbytes, c->stream, bt)));
+    PM_TRY(dev(launch_sort_count(c->fixed, d_pos, c->np, c->logn, c->tile_counts, c->sort_key,
+                                 c->sort_rank, c->stream, bt)));
+    PM_TRY(dev(launch_sort_scan(c->tile_counts, c->tiles, c->slice_start, c->tile_start,
+                                c->chunk_start, c->stream, bt)));
+    PM_TRY(dev(launch_sort_scatter(d_pos, d_vel, nullptr, c->np, c->sort_key, c->sort_rank,
+                                   c->slice_start, c->pos_tmp, c->vel_tmp, nullptr, c->stream,
+                                   bt)));
+    PM_TRY(dev(launch_sort_copy(static_cast<uint32_t*>(d_pos), d_vel, c->pos_tmp, c->vel_tmp,
+                                c->np, c->stream, bt)));
+    sorted = true;
+    return PM_OK;
+  };
+  if (!(flags & PM_CONTINUE)) {
+    PM_TRY(dev(launch_fill_zero(c->mass, 8 * c->ncell, c->stream, bt)));
+    if (c->fixed)
+      PM_TRY(dev(sorted ? launch_deposit_fixed_tiled(static_cast<const uint32_t*>(d_pos), c->np,
+                                                     c->logn, c->tmap,
+                                                     static_cast<unsigned long long*>(c->mass),
+                                                     c->stream, bt)
+                        : launch_deposit_fixed(static_cast<const uint32_t*>(d_pos), c->np,
+                                               c->logn,
+                                               static_cast<unsigned long long*>(c->mass),
+                                               c->stream, bt)));
+    else
+      PM_TRY(dev(sorted ? launch_deposit_f32_tiled(static_cast<const float*>(d_pos), c->np,
+                                                   c->logn, c->tmap,
+                                                   static_cast<float*>(c->mass), c->stream, bt)
+                        : launch_deposit_f32(static_cast<const float*>(d_pos), c->np, c->logn,
+                                             static_cast<float*>(c->mass), c->stream, bt)));
+    PM_TRY(fields(row(0)));
+  }
+  for (int i = 0; i < nactive; ++i) b->fields_ok[slots[i]] = 0;
+  GatherConst unused;
+  unused.fg = unused.fq = 0.0f;
+  unused.fd_units = 0.0;
+  for (int k = 0; k < nsteps; ++k) {
+    if (sort_every > 0 && k % sort_every == 0) PM_TRY(sort_all());
+    PM_TRY(dev(launch_fill_zero(c->mass, 8 * c->ncell, c->stream, bt)));
+    PM_TRY(dev(launch_gather(c->fixed, true, true, c->logn, d_pos, d_vel, c->phi, c->q, c->np,
+                             unused, sorted ? &c->tmap : nullptr, c->mass, c->stream, row(k))));
+    PM_TRY(fields(row(k)));
+  }
+  PM_TRY(dev(launch_gather(c->fixed, true, false, c->logn, d_pos, d_vel, c->phi, c->q, c->np,
+                           unused, sorted ? &c->tmap : nullptr, nullptr, c->stream, row(nsteps))));
+  for (int i = 0; i < nactive; ++i) {
+    b->fields_ok[slots[i]] = 1;
+    if (sorted) b->sorted[slots[i]] = 1;
+  }
+  return PM_OK;
+}
+
+pm_status pm_batch_destroy(pm_batch* b) {
+  if (!b) return PM_EINVAL;
+  delete b;
   return PM_OK;
 }
 

@@ -21,19 +21,22 @@
 
 namespace fdm {
 
-__global__ void __launch_bounds__(kBlock) k_fill_zero16(uint4* __restrict__ p, size_t n16) {
+__global__ void __launch_bounds__(kBlock) k_fill_zero16(uint4* __restrict__ p, size_t n16,
+                                                        Batch bt) {
+  p = woff(p, bt, bslot(bt));
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
     p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
-hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s, const Batch& bt) {
   // callers pass 16-byte multiples of 256-byte aligned buffers
   size_t n16 = bytes / 16;
   if (n16 == 0) return hipSuccess;
   size_t blocks = (n16 + kBlock - 1) / kBlock;
   if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(k_fill_zero16, dim3((unsigned)blocks), dim3(kBlock), 0, s, (uint4*)p, n16);
+  hipLaunchKernelGGL(k_fill_zero16, dim3((unsigned)blocks, bt.count), dim3(kBlock), 0, s,
+                     (uint4*)p, n16, bt);
   return hipGetLastError();
 }
 
@@ -42,7 +45,13 @@ __global__ void __launch_bounds__(kBlock) k_deposit_fixed(const uint32_t* __rest
                                                           const uint32_t* __restrict__ py,
                                                           const uint32_t* __restrict__ pz,
                                                           int64_t np,
-                                                          unsigned long long* __restrict__ mass) {
+                                                          unsigned long long* __restrict__ mass,
+                                                          Batch bt) {
+  const int sl = bslot(bt);
+  px = poff(px, bt, sl);
+  py = poff(py, bt, sl);
+  pz = poff(pz, bt, sl);
+  mass = woff(mass, bt, sl);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += stride) {
     int ix, iy, iz;
@@ -56,7 +65,13 @@ template <int LOGN>
 __global__ void __launch_bounds__(kBlock) k_deposit_f32(const float* __restrict__ px,
                                                         const float* __restrict__ py,
                                                         const float* __restrict__ pz,
-                                                        int64_t np, float* __restrict__ acc) {
+                                                        int64_t np, float* __restrict__ acc,
+                                                        Batch bt) {
+  const int sl = bslot(bt);
+  px = poff(px, bt, sl);
+  py = poff(py, bt, sl);
+  pz = poff(pz, bt, sl);
+  acc = woff(acc, bt, sl);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += stride) {
     int ix, iy, iz;
@@ -75,7 +90,7 @@ __global__ void __launch_bounds__(kBlock) k_deposit_f32(const float* __restrict_
 template <int LOGN, bool FIXED>
 __global__ void __launch_bounds__(kBlock) k_deposit_tiled(const void* __restrict__ pos,
                                                           int64_t np, TileMap tm,
-                                                          void* __restrict__ mass_v) {
+                                                          void* __restrict__ mass_v, Batch bt) {
   using T = typename std::conditional<FIXED, unsigned long long, float>::type;
   constexpr int N = 1 << LOGN;
   constexpr int MASK = N - 1;
@@ -83,7 +98,11 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiled(const void* __restrict
   constexpr int WX = TX + 1, WY = TY + 1, WZ = TZ + 1;
   constexpr int NTY = N / TY, NTZ = N / TZ;
   __shared__ T acc[WX * WY * WZ];
-  T* mass = static_cast<T*>(mass_v);
+  const int sl = bslot(bt);
+  pos = poff(pos, bt, sl);
+  T* mass = woff(static_cast<T*>(mass_v), bt, sl);
+  tm.start = woff(tm.start, bt, sl);
+  tm.chunk_start = woff(tm.chunk_start, bt, sl);
   int t;
   unsigned lo, hi;
   if (!chunk_of(tm, t, lo, hi)) return;
@@ -129,11 +148,11 @@ static unsigned grid_for(int64_t np) {
 }
 
 hipError_t launch_deposit_fixed(const uint32_t* pos, int64_t np, int logn,
-                                unsigned long long* mass, hipStream_t s) {
+                                unsigned long long* mass, hipStream_t s, const Batch& bt) {
   const unsigned g = grid_for(np);
-#define L_(LN)                                                                           \
-  hipLaunchKernelGGL(k_deposit_fixed<LN>, dim3(g), dim3(kBlock), 0, s, pos, pos + np, \
-                     pos + 2 * np, np, mass)
+#define L_(LN)                                                                                \
+  hipLaunchKernelGGL(k_deposit_fixed<LN>, dim3(g, bt.count), dim3(kBlock), 0, s, pos, pos + np, \
+                     pos + 2 * np, np, mass, bt)
   FDM_LOGN_SWITCH(logn, L_)
 #undef L_
   return hipGetLastError();
@@ -141,31 +160,31 @@ hipError_t launch_deposit_fixed(const uint32_t* pos, int64_t np, int logn,
 
 hipError_t launch_deposit_fixed_tiled(const uint32_t* pos, int64_t np, int logn,
                                       const TileMap& tm, unsigned long long* mass,
-                                      hipStream_t s) {
-  const dim3 g(tiled_grid(np, tm.tiles));
+                                      hipStream_t s, const Batch& bt) {
+  const dim3 g(tiled_grid(np, tm.tiles), bt.count);
 #define L_(LN) \
-  hipLaunchKernelGGL((k_deposit_tiled<LN, true>), g, dim3(kBlock), 0, s, pos, np, tm, mass)
+  hipLaunchKernelGGL((k_deposit_tiled<LN, true>), g, dim3(kBlock), 0, s, pos, np, tm, mass, bt)
   FDM_LOGN_SWITCH(logn, L_)
 #undef L_
   return hipGetLastError();
 }
 
 hipError_t launch_deposit_f32_tiled(const float* pos, int64_t np, int logn, const TileMap& tm,
-                                    float* acc, hipStream_t s) {
-  const dim3 g(tiled_grid(np, tm.tiles));
+                                    float* acc, hipStream_t s, const Batch& bt) {
+  const dim3 g(tiled_grid(np, tm.tiles), bt.count);
 #define L_(LN) \
-  hipLaunchKernelGGL((k_deposit_tiled<LN, false>), g, dim3(kBlock), 0, s, pos, np, tm, acc)
+  hipLaunchKernelGGL((k_deposit_tiled<LN, false>), g, dim3(kBlock), 0, s, pos, np, tm, acc, bt)
   FDM_LOGN_SWITCH(logn, L_)
 #undef L_
   return hipGetLastError();
 }
 
 hipError_t launch_deposit_f32(const float* pos, int64_t np, int logn, float* acc,
-                              hipStream_t s) {
+                              hipStream_t s, const Batch& bt) {
   const unsigned g = grid_for(np);
-#define L_(LN)                                                                           \
-  hipLaunchKernelGGL(k_deposit_f32<LN>, dim3(g), dim3(kBlock), 0, s, pos, pos + np, \
-                     pos + 2 * np, np, acc)
+#define L_(LN)                                                                              \
+  hipLaunchKernelGGL(k_deposit_f32<LN>, dim3(g, bt.count), dim3(kBlock), 0, s, pos, pos + np, \
+                     pos + 2 * np, np, acc, bt)
   FDM_LOGN_SWITCH(logn, L_)
 #undef L_
   return hipGetLastError();

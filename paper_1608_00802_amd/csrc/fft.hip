@@ -135,7 +135,14 @@ template <int LOGN, int SRC>
 __global__ void __launch_bounds__(kBlock) k_r2c_z(const void* __restrict__ in,
                                                   float* __restrict__ delta_out,
                                                   float2* __restrict__ spec,
-                                                  const float2* __restrict__ tw, DeltaConv conv) {
+                                                  const float2* __restrict__ tw, DeltaConv conv,
+                                                  Batch bt) {
+  {
+    const int sl = bslot(bt);
+    in = woff(in, bt, sl);
+    delta_out = woff(delta_out, bt, sl);
+    spec = woff(spec, bt, sl);
+  }
   constexpr int N = 1 << LOGN;
   constexpr int H = N / 2;
   constexpr int TZ = Tiles<N>::TZ;
@@ -190,7 +197,8 @@ __global__ void __launch_bounds__(kBlock) k_r2c_z(const void* __restrict__ in,
 // ---------------------------------------------------------------- passes 2, 4
 template <int LOGN, bool INV>
 __global__ void __launch_bounds__(kBlock) k_fft_y(float2* __restrict__ spec,
-                                                  const float2* __restrict__ tw) {
+                                                  const float2* __restrict__ tw, Batch bt) {
+  spec = woff(spec, bt, bslot(bt));
   constexpr int N = 1 << LOGN;
   constexpr int TY = Tiles<N>::TY;
   constexpr int LP = N + 1;
@@ -216,7 +224,8 @@ template <int LOGN>
 __global__ void __launch_bounds__(kBlock) k_fft_x_green(float2* __restrict__ spec,
                                                         const float2* __restrict__ tw,
                                                         const float* __restrict__ s2,
-                                                        float green_scale) {
+                                                        float green_scale, Batch bt) {
+  spec = woff(spec, bt, bslot(bt));
   constexpr int N = 1 << LOGN;
   constexpr int TC = Tiles<N>::TC;
   constexpr int LP = N + 1;
@@ -255,7 +264,12 @@ __global__ void __launch_bounds__(kBlock) k_fft_x_green(float2* __restrict__ spe
 template <int LOGN>
 __global__ void __launch_bounds__(kBlock) k_c2r_z(const float2* __restrict__ spec,
                                                   const float2* __restrict__ tw,
-                                                  float* __restrict__ out) {
+                                                  float* __restrict__ out, Batch bt) {
+  {
+    const int sl = bslot(bt);
+    spec = woff(spec, bt, sl);
+    out = woff(out, bt, sl);
+  }
   constexpr int N = 1 << LOGN;
   constexpr int H = N / 2;
   constexpr int TZ = Tiles<N>::TZ;
@@ -292,20 +306,20 @@ __global__ void __launch_bounds__(kBlock) k_c2r_z(const float2* __restrict__ spe
 
 // ---------------------------------------------------------------- launchers
 hipError_t launch_r2c_z(int logn, int src, const void* in, float* delta_out, float2* spec,
-                        const float2* tw, DeltaConv conv, hipStream_t s) {
+                        const float2* tw, DeltaConv conv, hipStream_t s, const Batch& bt) {
 #define L_(LN)                                                                          \
   {                                                                                     \
     constexpr int N_ = 1 << LN;                                                         \
-    dim3 g(N_ * (N_ / Tiles<N_>::TZ));                                                  \
+    dim3 g(N_ * (N_ / Tiles<N_>::TZ), bt.count);                                        \
     if (src == kSrcMass64)                                                              \
       hipLaunchKernelGGL((k_r2c_z<LN, kSrcMass64>), g, dim3(kBlock), 0, s, in, delta_out, \
-                         spec, tw, conv);                                               \
+                         spec, tw, conv, bt);                                           \
     else if (src == kSrcAcc32)                                                          \
       hipLaunchKernelGGL((k_r2c_z<LN, kSrcAcc32>), g, dim3(kBlock), 0, s, in, delta_out, \
-                         spec, tw, conv);                                               \
+                         spec, tw, conv, bt);                                           \
     else                                                                                \
       hipLaunchKernelGGL((k_r2c_z<LN, kSrcDelta>), g, dim3(kBlock), 0, s, in, delta_out, \
-                         spec, tw, conv);                                               \
+                         spec, tw, conv, bt);                                           \
   }
   FDM_LOGN_SWITCH(logn, L_)
 #undef L_
@@ -313,15 +327,15 @@ hipError_t launch_r2c_z(int logn, int src, const void* in, float* delta_out, flo
 }
 
 hipError_t launch_fft_y(int logn, float2* spec, const float2* tw, bool inverse,
-                        hipStream_t s) {
+                        hipStream_t s, const Batch& bt) {
 #define L_(LN)                                                                    \
   {                                                                               \
     constexpr int N_ = 1 << LN;                                                   \
-    dim3 g((N_ / 2 + 1) * (N_ / Tiles<N_>::TY));                                 \
+    dim3 g((N_ / 2 + 1) * (N_ / Tiles<N_>::TY), bt.count);                       \
     if (inverse)                                                                  \
-      hipLaunchKernelGGL((k_fft_y<LN, true>), g, dim3(kBlock), 0, s, spec, tw);   \
+      hipLaunchKernelGGL((k_fft_y<LN, true>), g, dim3(kBlock), 0, s, spec, tw, bt); \
     else                                                                          \
-      hipLaunchKernelGGL((k_fft_y<LN, false>), g, dim3(kBlock), 0, s, spec, tw);  \
+      hipLaunchKernelGGL((k_fft_y<LN, false>), g, dim3(kBlock), 0, s, spec, tw, bt); \
   }
   FDM_LOGN_SWITCH(logn, L_)
 #undef L_
@@ -329,13 +343,13 @@ hipError_t launch_fft_y(int logn, float2* spec, const float2* tw, bool inverse,
 }
 
 hipError_t launch_fft_x_green(int logn, float2* spec, const float2* tw, const float* s2,
-                              float green_scale, hipStream_t s) {
+                              float green_scale, hipStream_t s, const Batch& bt) {
 #define L_(LN)                                                                      \
   {                                                                                 \
     constexpr int N_ = 1 << LN;                                                     \
-    dim3 g((N_ / 2 + 1) * (N_ / Tiles<N_>::TC));                                    \
+    dim3 g((N_ / 2 + 1) * (N_ / Tiles<N_>::TC), bt.count);                          \
     hipLaunchKernelGGL((k_fft_x_green<LN>), g, dim3(kBlock), 0, s, spec, tw, s2,    \
-                       green_scale);                                                \
+                       green_scale, bt);                                            \
   }
   FDM_LOGN_SWITCH(logn, L_)
 #undef L_
@@ -343,12 +357,12 @@ hipError_t launch_fft_x_green(int logn, float2* spec, const float2* tw, const fl
 }
 
 hipError_t launch_c2r_z(int logn, const float2* spec, const float2* tw, float* out,
-                        hipStream_t s) {
+                        hipStream_t s, const Batch& bt) {
 #define L_(LN)                                                                  \
   {                                                                             \
     constexpr int N_ = 1 << LN;                                                 \
-    dim3 g(N_ * (N_ / Tiles<N_>::TZ));                                          \
-    hipLaunchKernelGGL((k_c2r_z<LN>), g, dim3(kBlock), 0, s, spec, tw, out);    \
+    dim3 g(N_ * (N_ / Tiles<N_>::TZ), bt.count);                                \
+    hipLaunchKernelGGL((k_c2r_z<LN>), g, dim3(kBlock), 0, s, spec, tw, out, bt); \
   }
   FDM_LOGN_SWITCH(logn, L_)
 #undef L_

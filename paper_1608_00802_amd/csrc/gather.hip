@@ -147,7 +147,22 @@ __global__ void __launch_bounds__(kBlock) k_gather(void* __restrict__ pos,
                                                    const float* __restrict__ phi,
                                                    const float* __restrict__ q, int64_t np,
                                                    GatherConst gc, float* __restrict__ acc,
-                                                   void* __restrict__ mass_v) {
+                                                   void* __restrict__ mass_v, Batch bt) {
+  {
+    const int sl = bslot(bt);
+    pos = poff(pos, bt, sl);
+    vel = poff(vel, bt, sl);
+    acc = poff(acc, bt, sl);
+    phi = woff(phi, bt, sl);
+    q = woff(q, bt, sl);
+    mass_v = woff(mass_v, bt, sl);
+    if (bt.consts) {
+      const SlotConst& sc = bt.consts[blockIdx.y];
+      gc.fg = sc.fg;
+      gc.fq = sc.fq;
+      gc.fd_units = sc.fd_units;
+    }
+  }
   using T = typename std::conditional<FIXED, unsigned long long, float>::type;
   constexpr int N = 1 << LOGN;
   constexpr int MASK = N - 1;
@@ -186,7 +201,24 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather_tiled(void* __restrict_
                                                          const float* __restrict__ q, int64_t np,
                                                          TileMap tm, GatherConst gc,
                                                          float* __restrict__ acc,
-                                                         void* __restrict__ mass_v) {
+                                                         void* __restrict__ mass_v, Batch bt) {
+  {
+    const int sl = bslot(bt);
+    pos = poff(pos, bt, sl);
+    vel = poff(vel, bt, sl);
+    acc = poff(acc, bt, sl);
+    phi = woff(phi, bt, sl);
+    q = woff(q, bt, sl);
+    mass_v = woff(mass_v, bt, sl);
+    tm.start = woff(tm.start, bt, sl);
+    tm.chunk_start = woff(tm.chunk_start, bt, sl);
+    if (bt.consts) {
+      const SlotConst& sc = bt.consts[blockIdx.y];
+      gc.fg = sc.fg;
+      gc.fq = sc.fq;
+      gc.fd_units = sc.fd_units;
+    }
+  }
   using T = typename std::conditional<FIXED, unsigned long long, float>::type;
   constexpr int N = 1 << LOGN;
   constexpr int MASK = N - 1;
@@ -269,65 +301,66 @@ static unsigned grid_particles(int64_t np) {
 template <int LN, int MODE, bool DEP>
 static void launch_mode_tiled(bool fixed, bool has_q, hipStream_t s, void* pos, float* vel,
                               const float* phi, const float* q, int64_t np, const TileMap& tm,
-                              const GatherConst& gc, float* acc, void* mass) {
-  const dim3 g(tiled_grid(np, tm.tiles));
+                              const GatherConst& gc, float* acc, void* mass, const Batch& bt) {
+  const dim3 g(tiled_grid(np, tm.tiles), bt.count);
   if (fixed && has_q)
     hipLaunchKernelGGL((k_gather_tiled<LN, true, true, MODE, DEP>), g, dim3(kGatherBlock), 0, s, pos,
-                       vel, phi, q, np, tm, gc, acc, mass);
+                       vel, phi, q, np, tm, gc, acc, mass, bt);
   else if (fixed)
     hipLaunchKernelGGL((k_gather_tiled<LN, true, false, MODE, DEP>), g, dim3(kGatherBlock), 0, s, pos,
-                       vel, phi, q, np, tm, gc, acc, mass);
+                       vel, phi, q, np, tm, gc, acc, mass, bt);
   else if (has_q)
     hipLaunchKernelGGL((k_gather_tiled<LN, false, true, MODE, DEP>), g, dim3(kGatherBlock), 0, s, pos,
-                       vel, phi, q, np, tm, gc, acc, mass);
+                       vel, phi, q, np, tm, gc, acc, mass, bt);
   else
     hipLaunchKernelGGL((k_gather_tiled<LN, false, false, MODE, DEP>), g, dim3(kGatherBlock), 0, s, pos,
-                       vel, phi, q, np, tm, gc, acc, mass);
+                       vel, phi, q, np, tm, gc, acc, mass, bt);
 }
 
 template <int LN, int MODE, bool DEP>
 static void launch_mode(bool fixed, bool has_q, dim3 g, hipStream_t s, void* pos, float* vel,
                         const float* phi, const float* q, int64_t np, const GatherConst& gc,
-                        float* acc, void* mass) {
+                        float* acc, void* mass, const Batch& bt) {
+  g.y = bt.count;
   if (fixed && has_q)
     hipLaunchKernelGGL((k_gather<LN, true, true, MODE, DEP>), g, dim3(kBlock), 0, s, pos, vel, phi,
-                       q, np, gc, acc, mass);
+                       q, np, gc, acc, mass, bt);
   else if (fixed)
     hipLaunchKernelGGL((k_gather<LN, true, false, MODE, DEP>), g, dim3(kBlock), 0, s, pos, vel,
-                       phi, q, np, gc, acc, mass);
+                       phi, q, np, gc, acc, mass, bt);
   else if (has_q)
     hipLaunchKernelGGL((k_gather<LN, false, true, MODE, DEP>), g, dim3(kBlock), 0, s, pos, vel,
-                       phi, q, np, gc, acc, mass);
+                       phi, q, np, gc, acc, mass, bt);
   else
     hipLaunchKernelGGL((k_gather<LN, false, false, MODE, DEP>), g, dim3(kBlock), 0, s, pos, vel,
-                       phi, q, np, gc, acc, mass);
+                       phi, q, np, gc, acc, mass, bt);
 }
 
 hipError_t launch_gather(bool fixed, bool has_q, bool drift, int logn, void* pos, float* vel,
                          const float* phi, const float* q, int64_t np, const GatherConst& gc,
-                         const TileMap* tm, void* deposit_mass, hipStream_t s) {
+                         const TileMap* tm, void* deposit_mass, hipStream_t s, const Batch& bt) {
   const dim3 g(grid_particles(np));
   const bool dep = drift && deposit_mass != nullptr;
 #define L_(LN)                                                                                 \
   {                                                                                            \
     if (tm && dep)                                                                             \
       launch_mode_tiled<LN, kKickDrift, true>(fixed, has_q, s, pos, vel, phi, q, np, *tm, gc,  \
-                                              nullptr, deposit_mass);                          \
+                                              nullptr, deposit_mass, bt);                      \
     else if (tm && drift)                                                                      \
       launch_mode_tiled<LN, kKickDrift, false>(fixed, has_q, s, pos, vel, phi, q, np, *tm, gc, \
-                                               nullptr, nullptr);                              \
+                                               nullptr, nullptr, bt);                          \
     else if (tm)                                                                               \
       launch_mode_tiled<LN, kKick, false>(fixed, has_q, s, pos, vel, phi, q, np, *tm, gc,      \
-                                          nullptr, nullptr);                                   \
+                                          nullptr, nullptr, bt);                               \
     else if (dep)                                                                              \
       launch_mode<LN, kKickDrift, true>(fixed, has_q, g, s, pos, vel, phi, q, np, gc, nullptr, \
-                                        deposit_mass);                                         \
+                                        deposit_mass, bt);                                     \
     else if (drift)                                                                            \
       launch_mode<LN, kKickDrift, false>(fixed, has_q, g, s, pos, vel, phi, q, np, gc,         \
-                                         nullptr, nullptr);                                    \
+                                         nullptr, nullptr, bt);                                \
     else                                                                                       \
       launch_mode<LN, kKick, false>(fixed, has_q, g, s, pos, vel, phi, q, np, gc, nullptr,     \
-                                    nullptr);                                                  \
+                                    nullptr, bt);                                              \
   }
   FDM_LOGN_SWITCH(logn, L_)
 #undef L_
@@ -344,7 +377,7 @@ hipError_t launch_force(bool fixed, bool has_q, int logn, const void* pos, const
   gc.fd_units = 0.0;
 #define L_(LN)                                                                            \
   launch_mode<LN, kForce, false>(fixed, has_q, g, s, const_cast<void*>(pos), nullptr, phi, q, \
-                                 np, gc, acc, nullptr)
+                                 np, gc, acc, nullptr, Batch())
   FDM_LOGN_SWITCH(logn, L_)
 #undef L_
   return hipGetLastError();
@@ -352,7 +385,12 @@ hipError_t launch_force(bool fixed, bool has_q, int logn, const void* pos, const
 
 // FP64 partial sums of |v|^2 per block.
 __global__ void __launch_bounds__(kBlock) k_kinetic(const float* __restrict__ vel, int64_t np,
-                                                    double* __restrict__ partials) {
+                                                    double* __restrict__ partials, Batch bt) {
+  {
+    const int sl = bslot(bt);
+    vel = poff(vel, bt, sl);
+    partials = woff(partials, bt, sl);
+  }
   __shared__ double red[kBlock / 64];
   double t = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -378,8 +416,9 @@ int kinetic_blocks(int64_t np) {
 }
 
 hipError_t launch_kinetic(const float* vel, int64_t np, double* partials, int nblocks,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(k_kinetic, dim3(nblocks), dim3(kBlock), 0, s, vel, np, partials);
+                          hipStream_t s, const Batch& bt) {
+  hipLaunchKernelGGL(k_kinetic, dim3(nblocks, bt.count), dim3(kBlock), 0, s, vel, np, partials,
+                     bt);
   return hipGetLastError();
 }
 

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 // Dispatch a runtime log2(N) to a template instantiation (N = 16..512).
 #define FDM_LOGN_SWITCH(logn, MACRO) \
   switch (logn) {                    \
@@ -53,6 +55,39 @@ __host__ __device__ constexpr int tile_count(int logn) {
          (1 << (logn - tile_lz(logn)));
 }
 
+// Per-slot constants of a batched launch (runs of one mesh size stepping
+// together); indexed by blockIdx.y, the slot's position in the launch.
+struct SlotConst {
+  float fg;         // kick factor on -grad(phi)
+  float fq;         // kick factor on -grad(Q)
+  double fd_units;  // drift factor times 2^(32 - log2 N) (fixed) or drift factor (float)
+  float qcoef;      // -(hbar/m)^2 / 2 in cells^2/time
+  float pad;
+  double qcoef_d;
+};
+
+// Batched launches: grid.y enumerates slots; every workspace pointer of slot
+// s is base + s * ws_stride bytes, every particle array base + s * part_stride.
+// The default (slots == nullptr) is a single run in slot 0.
+struct Batch {
+  const int* slots = nullptr;
+  long long ws_stride = 0;
+  long long part_stride = 0;
+  const SlotConst* consts = nullptr;
+  unsigned count = 1;
+};
+__device__ __forceinline__ int bslot(const Batch& b) { return b.slots ? b.slots[blockIdx.y] : 0; }
+template <class T>
+__device__ __forceinline__ T* woff(T* p, const Batch& b, int s) {
+  using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+  return p ? reinterpret_cast<T*>(reinterpret_cast<B*>(p) + (long long)s * b.ws_stride) : p;
+}
+template <class T>
+__device__ __forceinline__ T* poff(T* p, const Batch& b, int s) {
+  using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+  return p ? reinterpret_cast<T*>(reinterpret_cast<B*>(p) + (long long)s * b.part_stride) : p;
+}
+
 // Sources of the forward z-pass.
 enum ZSource : int {
   kSrcMass64 = 0,   // exact integer mass (fixed-point form)
@@ -84,11 +119,12 @@ struct GatherConst {
 };
 
 // ---- deposit.hip
-hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s, const Batch& bt = Batch());
 hipError_t launch_deposit_fixed(const uint32_t* pos, int64_t np, int logn,
-                                unsigned long long* mass, hipStream_t s);
+                                unsigned long long* mass, hipStream_t s,
+                                const Batch& bt = Batch());
 hipError_t launch_deposit_f32(const float* pos, int64_t np, int logn, float* acc,
-                              hipStream_t s);
+                              hipStream_t s, const Batch& bt = Batch());
 // Tiled variants.  The particle sort leaves tile ranges and their chunking:
 struct TileMap {
   const unsigned* start;        // [tiles + 1] first particle of each tile
@@ -131,52 +167,58 @@ __device__ __forceinline__ bool chunk_of(const TileMap& tm, int& tile, unsigned&
 
 hipError_t launch_deposit_fixed_tiled(const uint32_t* pos, int64_t np, int logn,
                                       const TileMap& tm, unsigned long long* mass,
-                                      hipStream_t s);
+                                      hipStream_t s, const Batch& bt = Batch());
 hipError_t launch_deposit_f32_tiled(const float* pos, int64_t np, int logn, const TileMap& tm,
-                                    float* acc, hipStream_t s);
+                                    float* acc, hipStream_t s, const Batch& bt = Batch());
 
 // ---- sort.hip
 // counts: [tiles * kSlices]; key[i] = tile * kSlices + slice
 hipError_t launch_sort_count(bool fixed, const void* pos, int64_t np, int logn,
-                             unsigned* counts, unsigned* key, unsigned* rank, hipStream_t s);
+                             unsigned* counts, unsigned* key, unsigned* rank, hipStream_t s,
+                             const Batch& bt = Batch());
 // slice_start: [tiles * kSlices + 1]; tile_start, chunk_start: [tiles + 1]
 hipError_t launch_sort_scan(const unsigned* counts, int tiles, unsigned* slice_start,
-                            unsigned* tile_start, unsigned* chunk_start, hipStream_t s);
+                            unsigned* tile_start, unsigned* chunk_start, hipStream_t s,
+                            const Batch& bt = Batch());
 hipError_t launch_sort_scatter(const void* pos, const float* vel, const int* ids, int64_t np,
                                const unsigned* key, const unsigned* rank,
                                const unsigned* slice_start, uint32_t* pos_out, float* vel_out,
-                               int* ids_out, hipStream_t s);
+                               int* ids_out, hipStream_t s, const Batch& bt = Batch());
+hipError_t launch_sort_copy(uint32_t* pos, float* vel, const uint32_t* pos_tmp,
+                            const float* vel_tmp, int64_t np, hipStream_t s, const Batch& bt);
 
 // ---- fft.hip
 // Forward transform of the density contrast and Poisson solve, written as
 // five passes over the half-spectrum spec[kz][kx][ky] (kz = 0..N/2).
 hipError_t launch_r2c_z(int logn, int src, const void* in, float* delta_out,
-                        float2* spec, const float2* tw, DeltaConv conv, hipStream_t s);
+                        float2* spec, const float2* tw, DeltaConv conv, hipStream_t s,
+                        const Batch& bt = Batch());
 hipError_t launch_fft_y(int logn, float2* spec, const float2* tw, bool inverse,
-                        hipStream_t s);
+                        hipStream_t s, const Batch& bt = Batch());
 hipError_t launch_fft_x_green(int logn, float2* spec, const float2* tw, const float* s2,
-                              float green_scale, hipStream_t s);
+                              float green_scale, hipStream_t s, const Batch& bt = Batch());
 hipError_t launch_c2r_z(int logn, const float2* spec, const float2* tw, float* out,
-                        hipStream_t s);
+                        hipStream_t s, const Batch& bt = Batch());
 
 // ---- stencil.hip
 hipError_t launch_qpot(int logn, bool fixed, bool energy, const float* delta,
                        const long long* mass, const float* phi, float* q,
-                       const QConst& qc, double* partials, hipStream_t s);
+                       const QConst& qc, double* partials, hipStream_t s,
+                       const Batch& bt = Batch());
 int qpot_blocks(int logn);
 hipError_t launch_reduce(const double* partials, int nblocks, int ncomp, double* out,
-                         hipStream_t s);
+                         hipStream_t s, const Batch& bt = Batch());
 
 // ---- gather.hip
 hipError_t launch_gather(bool fixed, bool has_q, bool drift, int logn, void* pos,
                          float* vel, const float* phi, const float* q, int64_t np,
                          const GatherConst& gc, const TileMap* tm, void* deposit_mass,
-                         hipStream_t s);
+                         hipStream_t s, const Batch& bt = Batch());
 hipError_t launch_force(bool fixed, bool has_q, int logn, const void* pos,
                         const float* phi, const float* q, int64_t np, float fg, float fq,
                         float* acc, hipStream_t s);
 hipError_t launch_kinetic(const float* vel, int64_t np, double* partials, int nblocks,
-                          hipStream_t s);
+                          hipStream_t s, const Batch& bt = Batch());
 int kinetic_blocks(int64_t np);
 
 }  // namespace fdm

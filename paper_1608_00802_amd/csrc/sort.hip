@@ -32,7 +32,14 @@ __global__ void __launch_bounds__(kBlock) k_sort_count(const void* __restrict__ 
                                                        int logn,
                                                        unsigned* __restrict__ counts,
                                                        unsigned* __restrict__ key_out,
-                                                       unsigned* __restrict__ rank_out) {
+                                                       unsigned* __restrict__ rank_out, Batch bt) {
+  {
+    const int sl = bslot(bt);
+    pos = poff(pos, bt, sl);
+    counts = woff(counts, bt, sl);
+    key_out = woff(key_out, bt, sl);
+    rank_out = woff(rank_out, bt, sl);
+  }
   const int lane = threadIdx.x & 63;
   const int lx = tile_lx(logn), ly = tile_ly(logn), lz = tile_lz(logn);
   const int ty_n = 1 << (logn - ly), tz_n = 1 << (logn - lz);
@@ -95,7 +102,15 @@ __global__ void __launch_bounds__(kScanThreads) k_sort_scan(const unsigned* __re
                                                            int tiles,
                                                            unsigned* __restrict__ slice_start,
                                                            unsigned* __restrict__ tile_start,
-                                                           unsigned* __restrict__ chunk_start) {
+                                                           unsigned* __restrict__ chunk_start,
+                                                           Batch bt) {
+  {
+    const int sl = bslot(bt);
+    counts = woff(counts, bt, sl);
+    slice_start = woff(slice_start, bt, sl);
+    tile_start = woff(tile_start, bt, sl);
+    chunk_start = woff(chunk_start, bt, sl);
+  }
   __shared__ unsigned pa[kScanThreads], pb[kScanThreads];
   const int per = (tiles + kScanThreads - 1) / kScanThreads;
   const int lo = threadIdx.x * per;
@@ -145,7 +160,17 @@ __global__ void __launch_bounds__(kBlock) k_sort_scatter(
     const void* __restrict__ pos, const float* __restrict__ vel, const int* __restrict__ ids,
     int64_t np, const unsigned* __restrict__ key, const unsigned* __restrict__ rank,
     const unsigned* __restrict__ slice_start, uint32_t* __restrict__ pos_out,
-    float* __restrict__ vel_out, int* __restrict__ ids_out) {
+    float* __restrict__ vel_out, int* __restrict__ ids_out, Batch bt) {
+  {
+    const int sl = bslot(bt);
+    pos = poff(pos, bt, sl);
+    vel = poff(vel, bt, sl);
+    key = woff(key, bt, sl);
+    rank = woff(rank, bt, sl);
+    slice_start = woff(slice_start, bt, sl);
+    pos_out = woff(pos_out, bt, sl);
+    vel_out = woff(vel_out, bt, sl);
+  }
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += stride) {
     const int64_t dst = (int64_t)slice_start[key[i]] + rank[i];
@@ -166,34 +191,64 @@ static unsigned grid_p(int64_t np) {
 }
 
 hipError_t launch_sort_count(bool fixed, const void* pos, int64_t np, int logn,
-                             unsigned* counts, unsigned* key, unsigned* rank, hipStream_t s) {
+                             unsigned* counts, unsigned* key, unsigned* rank, hipStream_t s,
+                             const Batch& bt) {
+  const dim3 g(grid_p(np), bt.count);
   if (fixed)
-    hipLaunchKernelGGL(k_sort_count<true>, dim3(grid_p(np)), dim3(kBlock), 0, s, pos, np, logn,
-                       counts, key, rank);
+    hipLaunchKernelGGL(k_sort_count<true>, g, dim3(kBlock), 0, s, pos, np, logn, counts, key,
+                       rank, bt);
   else
-    hipLaunchKernelGGL(k_sort_count<false>, dim3(grid_p(np)), dim3(kBlock), 0, s, pos, np, logn,
-                       counts, key, rank);
+    hipLaunchKernelGGL(k_sort_count<false>, g, dim3(kBlock), 0, s, pos, np, logn, counts, key,
+                       rank, bt);
   return hipGetLastError();
 }
 
 hipError_t launch_sort_scan(const unsigned* counts, int tiles, unsigned* slice_start,
-                            unsigned* tile_start, unsigned* chunk_start, hipStream_t s) {
-  hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(kScanThreads), 0, s, counts, tiles, slice_start,
-                     tile_start, chunk_start);
+                            unsigned* tile_start, unsigned* chunk_start, hipStream_t s,
+                            const Batch& bt) {
+  hipLaunchKernelGGL(k_sort_scan, dim3(1, bt.count), dim3(kScanThreads), 0, s, counts, tiles,
+                     slice_start, tile_start, chunk_start, bt);
   return hipGetLastError();
 }
 
 hipError_t launch_sort_scatter(const void* pos, const float* vel, const int* ids, int64_t np,
                                const unsigned* key, const unsigned* rank, const unsigned* start,
                                uint32_t* pos_out, float* vel_out, int* ids_out,
-                               hipStream_t s) {
-  // positions are moved as 32-bit words in both forms
-  if (ids)
-    hipLaunchKernelGGL((k_sort_scatter<true, true>), dim3(grid_p(np)), dim3(kBlock), 0, s, pos,
-                       vel, ids, np, key, rank, start, pos_out, vel_out, ids_out);
+                               hipStream_t s, const Batch& bt) {
+  // positions are moved as 32-bit words in both forms; ids only for single runs
+  const dim3 g(grid_p(np), bt.count);
+  if (ids && !bt.slots)
+    hipLaunchKernelGGL((k_sort_scatter<true, true>), g, dim3(kBlock), 0, s, pos, vel, ids, np,
+                       key, rank, start, pos_out, vel_out, ids_out, bt);
   else
-    hipLaunchKernelGGL((k_sort_scatter<true, false>), dim3(grid_p(np)), dim3(kBlock), 0, s, pos,
-                       vel, ids, np, key, rank, start, pos_out, vel_out, ids_out);
+    hipLaunchKernelGGL((k_sort_scatter<true, false>), g, dim3(kBlock), 0, s, pos, vel, ids, np,
+                       key, rank, start, pos_out, vel_out, ids_out, bt);
+  return hipGetLastError();
+}
+
+// Copy the sorted particle copies back (batched launches; single runs use a
+// device-to-device memcpy).
+__global__ void __launch_bounds__(kBlock) k_sort_copy(uint32_t* __restrict__ pos,
+                                                      float* __restrict__ vel,
+                                                      const uint32_t* __restrict__ pos_tmp,
+                                                      const float* __restrict__ vel_tmp,
+                                                      int64_t n3, Batch bt) {
+  const int sl = bslot(bt);
+  pos = poff(pos, bt, sl);
+  vel = poff(vel, bt, sl);
+  pos_tmp = woff(pos_tmp, bt, sl);
+  vel_tmp = woff(vel_tmp, bt, sl);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n3; i += stride) {
+    pos[i] = pos_tmp[i];
+    vel[i] = vel_tmp[i];
+  }
+}
+
+hipError_t launch_sort_copy(uint32_t* pos, float* vel, const uint32_t* pos_tmp,
+                            const float* vel_tmp, int64_t np, hipStream_t s, const Batch& bt) {
+  hipLaunchKernelGGL(k_sort_copy, dim3(grid_p(3 * np), bt.count), dim3(kBlock), 0, s, pos, vel,
+                     pos_tmp, vel_tmp, 3 * np, bt);
   return hipGetLastError();
 }
 

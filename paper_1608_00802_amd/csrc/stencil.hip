@@ -35,7 +35,19 @@ __global__ void __launch_bounds__(kBlock) k_qpot(const float* __restrict__ delta
                                                  const long long* __restrict__ mass,
                                                  const float* __restrict__ phi,
                                                  float* __restrict__ q, QConst qc,
-                                                 double* __restrict__ partials) {
+                                                 double* __restrict__ partials, Batch bt) {
+  {
+    const int sl = bslot(bt);
+    delta = woff(delta, bt, sl);
+    mass = woff(mass, bt, sl);
+    phi = woff(phi, bt, sl);
+    q = woff(q, bt, sl);
+    partials = woff(partials, bt, sl);
+    if (bt.consts) {
+      qc.coef = bt.consts[blockIdx.y].qcoef;
+      qc.coef_d = bt.consts[blockIdx.y].qcoef_d;
+    }
+  }
   constexpr int N = 1 << LOGN;
   constexpr int MASK = N - 1;
   const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
@@ -117,7 +129,19 @@ __global__ void __launch_bounds__(kBlock) k_qpot_tiled(const float* __restrict__
                                                        const long long* __restrict__ mass,
                                                        const float* __restrict__ phi,
                                                        float* __restrict__ q, QConst qc,
-                                                       double* __restrict__ partials) {
+                                                       double* __restrict__ partials, Batch bt) {
+  {
+    const int sl = bslot(bt);
+    delta = woff(delta, bt, sl);
+    mass = woff(mass, bt, sl);
+    phi = woff(phi, bt, sl);
+    q = woff(q, bt, sl);
+    partials = woff(partials, bt, sl);
+    if (bt.consts) {
+      qc.coef = bt.consts[blockIdx.y].qcoef;
+      qc.coef_d = bt.consts[blockIdx.y].qcoef_d;
+    }
+  }
   constexpr int N = 1 << LOGN;
   constexpr int MASK = N - 1;
   constexpr int PY = QY + 2, PZ = QZ + 2;
@@ -213,24 +237,24 @@ int qpot_blocks(int logn) {
 
 hipError_t launch_qpot(int logn, bool fixed, bool energy, const float* delta,
                        const long long* mass, const float* phi, float* q, const QConst& qc,
-                       double* partials, hipStream_t s) {
-  const dim3 g((unsigned)qpot_blocks(logn));
+                       double* partials, hipStream_t s, const Batch& bt) {
+  const dim3 g((unsigned)qpot_blocks(logn), bt.count);
 #ifndef FDM_QPOT_SIMPLE
   if (logn >= 5) {
 #define T_(LN)                                                                               \
   {                                                                                          \
     if (fixed && energy)                                                                     \
       hipLaunchKernelGGL((k_qpot_tiled<LN, true, true>), g, dim3(kBlock), 0, s, delta, mass,  \
-                         phi, q, qc, partials);                                              \
+                         phi, q, qc, partials, bt);                                              \
     else if (fixed)                                                                          \
       hipLaunchKernelGGL((k_qpot_tiled<LN, true, false>), g, dim3(kBlock), 0, s, delta, mass, \
-                         phi, q, qc, partials);                                              \
+                         phi, q, qc, partials, bt);                                              \
     else if (energy)                                                                         \
       hipLaunchKernelGGL((k_qpot_tiled<LN, false, true>), g, dim3(kBlock), 0, s, delta, mass, \
-                         phi, q, qc, partials);                                              \
+                         phi, q, qc, partials, bt);                                              \
     else                                                                                     \
       hipLaunchKernelGGL((k_qpot_tiled<LN, false, false>), g, dim3(kBlock), 0, s, delta,     \
-                         mass, phi, q, qc, partials);                                        \
+                         mass, phi, q, qc, partials, bt);                                        \
   }
     switch (logn) {
       case 5: T_(5); break;
@@ -248,16 +272,16 @@ hipError_t launch_qpot(int logn, bool fixed, bool energy, const float* delta,
   {                                                                                       \
     if (fixed && energy)                                                                  \
       hipLaunchKernelGGL((k_qpot<LN, true, true>), g, dim3(kBlock), 0, s, delta, mass, phi, \
-                         q, qc, partials);                                                \
+                         q, qc, partials, bt);                                            \
     else if (fixed)                                                                       \
       hipLaunchKernelGGL((k_qpot<LN, true, false>), g, dim3(kBlock), 0, s, delta, mass,   \
-                         phi, q, qc, partials);                                           \
+                         phi, q, qc, partials, bt);                                           \
     else if (energy)                                                                      \
       hipLaunchKernelGGL((k_qpot<LN, false, true>), g, dim3(kBlock), 0, s, delta, mass,   \
-                         phi, q, qc, partials);                                           \
+                         phi, q, qc, partials, bt);                                           \
     else                                                                                  \
       hipLaunchKernelGGL((k_qpot<LN, false, false>), g, dim3(kBlock), 0, s, delta, mass,  \
-                         phi, q, qc, partials);                                           \
+                         phi, q, qc, partials, bt);                                           \
   }
   FDM_LOGN_SWITCH(logn, L_)
 #undef L_
@@ -267,7 +291,12 @@ hipError_t launch_qpot(int logn, bool fixed, bool energy, const float* delta,
 // Sum ncomp interleaved components of nblocks partials, fixed order.
 __global__ void __launch_bounds__(kBlock) k_reduce(const double* __restrict__ partials,
                                                    int nblocks, int ncomp,
-                                                   double* __restrict__ out) {
+                                                   double* __restrict__ out, Batch bt) {
+  {
+    const int sl = bslot(bt);
+    partials = woff(partials, bt, sl);
+    out = woff(out, bt, sl);
+  }
   __shared__ double red[kBlock];
   for (int c = 0; c < ncomp; ++c) {
     double t = 0.0;
@@ -284,8 +313,9 @@ __global__ void __launch_bounds__(kBlock) k_reduce(const double* __restrict__ pa
 }
 
 hipError_t launch_reduce(const double* partials, int nblocks, int ncomp, double* out,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, partials, nblocks, ncomp, out);
+                         hipStream_t s, const Batch& bt) {
+  hipLaunchKernelGGL(k_reduce, dim3(1, bt.count), dim3(kBlock), 0, s, partials, nblocks, ncomp,
+                     out, bt);
   return hipGetLastError();
 }
 
