@@ -92,6 +92,12 @@ struct pm_batch {
   SlotConst* d_consts;         // device [(max steps + 1) * slots]
   std::vector<double> box, hm;  // per slot, hm in cells^2/time
   std::vector<char> fields_ok, sorted;
+  // pinned staging of the per-call slot list and constant table (two
+  // buffers, so the host fills one while the other's copy is queued);
+  // pageable sources would make every call wait for the stream
+  char* h_stage[2] = {nullptr, nullptr};
+  hipEvent_t h_done[2] = {nullptr, nullptr};
+  int h_next = 0;
 };
 
 namespace {
@@ -346,6 +352,18 @@ pm_status copy_out(pm_ctx* c, float* dst, const float* src) {
 size_t batch_header(int slots) {
   return align_up(4 * (size_t)slots) + align_up(sizeof(SlotConst) * (PM_BATCH_MAX_STEPS + 1) *
                                                 (size_t)slots);
+}
+
+// Release a batch's host resources once its queued uploads are done.
+void batch_free(pm_batch* b) {
+  for (int i = 0; i < 2; ++i) {
+    if (b->h_done[i]) {
+      (void)hipEventSynchronize(b->h_done[i]);
+      (void)hipEventDestroy(b->h_done[i]);
+    }
+    if (b->h_stage[i]) (void)hipHostFree(b->h_stage[i]);
+  }
+  delete b;
 }
 
 // Fill a context for the workspace region at base (layout_for(*params)),
@@ -685,6 +703,13 @@ pm_status pm_batch_init(const pm_params* params, int32_t slots, void* d_workspac
     delete b;
     return st;
   }
+  for (int i = 0; i < 2; ++i) {
+    if (hipHostMalloc(reinterpret_cast<void**>(&b->h_stage[i]), header) != hipSuccess ||
+        hipEventCreateWithFlags(&b->h_done[i], hipEventDisableTiming) != hipSuccess) {
+      batch_free(b);
+      return PM_EDEVICE;
+    }
+  }
   b->box.assign(slots, params->box);
   b->hm.assign(slots, b->base.hm);
   b->fields_ok.assign(slots, 0);
@@ -763,10 +788,19 @@ pm_status pm_batch_step(pm_batch* b, void* d_pos, float* d_vel, int32_t nactive,
       }
     }
   }
-  PM_TRY(dev(hipMemcpyAsync(b->d_slots, slots, 4 * (size_t)nactive, hipMemcpyHostToDevice,
-                            c->stream)));
-  PM_TRY(dev(hipMemcpyAsync(b->d_consts, tab.data(), sizeof(SlotConst) * tab.size(),
-                            hipMemcpyHostToDevice, c->stream)));
+  {
+    // the buffer's previous copy was queued two calls ago; wait for it
+    const int hb = b->h_next;
+    b->h_next ^= 1;
+    PM_TRY(dev(hipEventSynchronize(b->h_done[hb])));
+    char* h = b->h_stage[hb];
+    const size_t coff = (size_t)(reinterpret_cast<char*>(b->d_consts) - b->ws);
+    memcpy(h, slots, 4 * (size_t)nactive);
+    memcpy(h + coff, tab.data(), sizeof(SlotConst) * tab.size());
+    PM_TRY(dev(hipMemcpyAsync(b->ws, h, coff + sizeof(SlotConst) * tab.size(),
+                              hipMemcpyHostToDevice, c->stream)));
+    PM_TRY(dev(hipEventRecord(b->h_done[hb], c->stream)));
+  }
   Batch bt;
   bt.slots = b->d_slots;
   bt.ws_stride = (long long)b->slot_stride;
@@ -846,7 +880,7 @@ pm_status pm_batch_step(pm_batch* b, void* d_pos, float* d_vel, int32_t nactive,
 
 pm_status pm_batch_destroy(pm_batch* b) {
   if (!b) return PM_EINVAL;
-  delete b;
+  batch_free(b);
   return PM_OK;
 }
 
