@@ -60,7 +60,8 @@ struct pm_ctx {
   float* s2;
   double* partials;  // energy partial sums
   double* result;    // reduced energies (device)
-  unsigned* tile_counts;  // [tiles * kSlices]
+  unsigned* tile_counts;  // [kSlices][count_stride(tiles)]
+  unsigned* scan_sums;    // [2 * scan_blocks(tiles)]
   unsigned* slice_start;  // [tiles * kSlices + 1]
   unsigned* tile_start;   // [tiles + 1], valid once sorted
   unsigned* chunk_start;  // [tiles + 1]
@@ -113,7 +114,7 @@ int ilog2_exact(int n) {
 }
 
 struct Layout {
-  size_t mass, delta, phi, q, spec, tw, s2, partials, result, tile_counts, slice_start,
+  size_t mass, delta, phi, q, spec, tw, s2, partials, result, tile_counts, scan_sums, slice_start,
       tile_start, chunk_start, sort_key, sort_rank, pos_tmp, vel_tmp, ids_tmp, total;
 };
 
@@ -140,7 +141,8 @@ Layout layout_for(const pm_params& p) {
   const int logn = ilog2_exact(p.n_mesh);
   const size_t tiles = logn > 0 ? (size_t)tile_count(logn) : 1;
   const size_t np = (size_t)(p.n_part > 0 ? p.n_part : 1);
-  L.tile_counts = take(4 * tiles * kSlices);
+  L.tile_counts = take(4 * (size_t)kSlices * count_stride((int)tiles));
+  L.scan_sums = take(8 * (size_t)scan_blocks((int)tiles));
   L.slice_start = take(4 * (tiles * kSlices + 1));
   L.tile_start = take(4 * (tiles + 1));
   L.chunk_start = take(4 * (tiles + 1));
@@ -407,6 +409,7 @@ pm_status ctx_setup(pm_ctx* c, const pm_params* params, char* base, hipStream_t 
   c->partials = reinterpret_cast<double*>(base + L.partials);
   c->result = reinterpret_cast<double*>(base + L.result);
   c->tile_counts = reinterpret_cast<unsigned*>(base + L.tile_counts);
+  c->scan_sums = reinterpret_cast<unsigned*>(base + L.scan_sums);
   c->slice_start = reinterpret_cast<unsigned*>(base + L.slice_start);
   c->tile_start = reinterpret_cast<unsigned*>(base + L.tile_start);
   c->chunk_start = reinterpret_cast<unsigned*>(base + L.chunk_start);
@@ -574,14 +577,14 @@ pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int
 
 pm_status pm_sort(pm_ctx* c, void* d_pos, float* d_vel, int32_t* d_ids) {
   if (!c || !d_pos || !d_vel) return PM_EINVAL;
-  const size_t cbytes = (4 * (size_t)c->tiles * kSlices + 15) & ~(size_t)15;
+  const size_t cbytes = 4 * (size_t)kSlices * count_stride(c->tiles);
   PM_TRY(timed(c, kcFill, [&] { return launch_fill_zero(c->tile_counts, cbytes, c->stream); }));
   PM_TRY(timed(c, kcSortCount, [&] {
     return launch_sort_count(c->fixed, d_pos, c->np, c->logn, c->tile_counts, c->sort_key,
                              c->sort_rank, c->stream);
   }));
   PM_TRY(timed(c, kcSortScan, [&] {
-    return launch_sort_scan(c->tile_counts, c->tiles, c->slice_start, c->tile_start,
+    return launch_sort_scan(c->tile_counts, c->tiles, c->scan_sums, c->slice_start, c->tile_start,
                             c->chunk_start, c->stream);
   }));
   PM_TRY(timed(c, kcSortScatter, [&] {
@@ -825,11 +828,11 @@ pm_status pm_batch_step(pm_batch* b, void* d_pos, float* d_vel, int32_t nactive,
                            c->partials, c->stream, bq));
   };
   auto sort_all = [&]() -> pm_status {
-    const size_t cbytes = (4 * (size_t)c->tiles * kSlices + 15) & ~(size_t)15;
+    const size_t cbytes = 4 * (size_t)kSlices * count_stride(c->tiles);
     PM_TRY(dev(launch_fill_zero(c->tile_counts, cbytes, c->stream, bt)));
     PM_TRY(dev(launch_sort_count(c->fixed, d_pos, c->np, c->logn, c->tile_counts, c->sort_key,
                                  c->sort_rank, c->stream, bt)));
-    PM_TRY(dev(launch_sort_scan(c->tile_counts, c->tiles, c->slice_start, c->tile_start,
+    PM_TRY(dev(launch_sort_scan(c->tile_counts, c->tiles, c->scan_sums, c->slice_start, c->tile_start,
                                 c->chunk_start, c->stream, bt)));
     PM_TRY(dev(launch_sort_scatter(d_pos, d_vel, nullptr, c->np, c->sort_key, c->sort_rank,
                                    c->slice_start, c->pos_tmp, c->vel_tmp, nullptr, c->stream,

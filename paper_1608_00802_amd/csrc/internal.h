@@ -47,6 +47,12 @@ constexpr int kChunk = 4096;
 // The sort counts each tile in kSlices sub-counters (chosen by block) to
 // spread same-address atomics on densely populated tiles.
 constexpr int kSlices = 16;
+// Counters of one slice are count_stride(tiles) apart (a multiple of 32
+// counters: the slices of a tile sit in different 128-byte lines).
+__host__ __device__ constexpr int count_stride(int tiles) { return (tiles + 31) & ~31; }
+// Blocks of the two scan kernels (256 tiles each), and their scratch of two
+// counters per block.
+__host__ __device__ constexpr int scan_blocks(int tiles) { return (tiles + 255) / 256; }
 __host__ __device__ constexpr int tile_lx(int logn) { return logn < kTileLX ? logn : kTileLX; }
 __host__ __device__ constexpr int tile_ly(int logn) { return logn < kTileLY ? logn : kTileLY; }
 __host__ __device__ constexpr int tile_lz(int logn) { return logn < kTileLZ ? logn : kTileLZ; }
@@ -172,14 +178,15 @@ hipError_t launch_deposit_f32_tiled(const float* pos, int64_t np, int logn, cons
                                     float* acc, hipStream_t s, const Batch& bt = Batch());
 
 // ---- sort.hip
-// counts: [tiles * kSlices]; key[i] = tile * kSlices + slice
+// counts: [kSlices][count_stride(tiles)]; key[i] = tile * kSlices + slice
 hipError_t launch_sort_count(bool fixed, const void* pos, int64_t np, int logn,
                              unsigned* counts, unsigned* key, unsigned* rank, hipStream_t s,
                              const Batch& bt = Batch());
-// slice_start: [tiles * kSlices + 1]; tile_start, chunk_start: [tiles + 1]
-hipError_t launch_sort_scan(const unsigned* counts, int tiles, unsigned* slice_start,
-                            unsigned* tile_start, unsigned* chunk_start, hipStream_t s,
-                            const Batch& bt = Batch());
+// slice_start: [tiles * kSlices + 1]; tile_start, chunk_start: [tiles + 1];
+// sums: scratch of 2 * scan_blocks(tiles) counters
+hipError_t launch_sort_scan(const unsigned* counts, int tiles, unsigned* sums,
+                            unsigned* slice_start, unsigned* tile_start, unsigned* chunk_start,
+                            hipStream_t s, const Batch& bt = Batch());
 hipError_t launch_sort_scatter(const void* pos, const float* vel, const int* ids, int64_t np,
                                const unsigned* key, const unsigned* rank,
                                const unsigned* slice_start, uint32_t* pos_out, float* vel_out,

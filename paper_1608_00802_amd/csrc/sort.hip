@@ -1,21 +1,36 @@
 // Counting sort of the particles by mesh tile (kTileLX/LY/LZ), so that
 // the deposit and the gather can stage a tile's mesh window in LDS.
 //
-//   1. count:   key = (tile of the particle's cell, slice = block mod
-//               kSlices); rank within the key from a wave-aggregated atomic
-//               on its counter (runs of equal keys among consecutive lanes
-//               take one atomic for the run).
+//   1. count:   a block takes a contiguous range of kCountPer * kCountBlock
+//               particles and counts them per tile in an LDS hash table
+//               (runs of equal tiles among consecutive lanes take one LDS
+//               atomic); then one device atomic per distinct tile of the
+//               block reserves the block's ranks on the counter of its
+//               slice (block mod kSlices).  Counters are slice-major, so the
+//               slices of a tile lie in different cache lines.
 //   2. scan:    exclusive prefix sums of the sliced counts, of the tile
-//               counts and of the chunks per tile (one block).
+//               counts and of the chunks per tile (reduce per block of
+//               tiles, then a down-sweep that adds the block offsets).
 //   3. scatter: particle -> slice_start[key] + rank in the workspace copies;
 //               a tile's slices are adjacent, so each tile stays contiguous.
 //
-// The order inside a tile depends on atomic scheduling; the set of particles
-// per tile does not, and no result of the step depends on the order (the
-// integer deposit is order-independent and the push is per particle).
+// Device atomics on one cache line serialise across the whole chip, and a
+// densely populated tile holds millions of particles, so the count keeps
+// them to one per (block, tile).  The order inside a tile depends on atomic
+// scheduling; the set of particles per tile does not, and no result of the
+// step depends on the order (the integer deposit is order-independent and
+// the push is per particle).
 #include "internal.h"
 
 namespace fdm {
+
+constexpr int kCountBlock = 256;
+constexpr int kCountPer = 16;                 // particles per thread
+constexpr int kHashBits = 9;
+constexpr int kHash = 1 << kHashBits;        // LDS hash slots per block
+constexpr int kProbe = 16;
+constexpr unsigned kEmpty = 0xffffffffu;
+constexpr int kScanBlock = 256;               // tiles per scan block
 
 template <bool FIXED>
 __device__ __forceinline__ int cell_of(const void* pos, int64_t np, int64_t i, int d, int logn) {
@@ -27,12 +42,26 @@ __device__ __forceinline__ int cell_of(const void* pos, int64_t np, int64_t i, i
   }
 }
 
+// Slot of key in the block's hash table (inserted if absent), kEmpty if the
+// probe sequence is full.
+__device__ __forceinline__ unsigned hash_slot(unsigned* hkey, unsigned key) {
+  unsigned h = (key * 2654435761u) >> (32 - kHashBits);
+  for (int k = 0; k < kProbe; ++k) {
+    const unsigned cur = hkey[h] == key ? key : atomicCAS(&hkey[h], kEmpty, key);
+    if (cur == kEmpty || cur == key) return h;
+    h = (h + 1) & (kHash - 1);
+  }
+  return kEmpty;
+}
+
 template <bool FIXED>
-__global__ void __launch_bounds__(kBlock) k_sort_count(const void* __restrict__ pos, int64_t np,
-                                                       int logn,
-                                                       unsigned* __restrict__ counts,
-                                                       unsigned* __restrict__ key_out,
-                                                       unsigned* __restrict__ rank_out, Batch bt) {
+__global__ void __launch_bounds__(kCountBlock) k_sort_count(const void* __restrict__ pos,
+                                                            int64_t np, int logn,
+                                                            unsigned* __restrict__ counts,
+                                                            int cstride,
+                                                            unsigned* __restrict__ key_out,
+                                                            unsigned* __restrict__ rank_out,
+                                                            Batch bt) {
   {
     const int sl = bslot(bt);
     pos = poff(pos, bt, sl);
@@ -40,21 +69,31 @@ __global__ void __launch_bounds__(kBlock) k_sort_count(const void* __restrict__ 
     key_out = woff(key_out, bt, sl);
     rank_out = woff(rank_out, bt, sl);
   }
+  __shared__ unsigned hkey[kHash], hcnt[kHash];
+  for (int i = threadIdx.x; i < kHash; i += kCountBlock) {
+    hkey[i] = kEmpty;
+    hcnt[i] = 0;
+  }
+  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int lx = tile_lx(logn), ly = tile_ly(logn), lz = tile_lz(logn);
   const int ty_n = 1 << (logn - ly), tz_n = 1 << (logn - lz);
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  // every lane of a wave runs every iteration (uniform trip count), so the
-  // cross-lane operations below always see the full wave
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < np; base += stride) {
-    const int64_t i = base + threadIdx.x;
+  const unsigned slice = blockIdx.x % kSlices;
+  unsigned* cnt = counts + (size_t)slice * cstride;
+  const int64_t base = (int64_t)blockIdx.x * (kCountBlock * kCountPer) + threadIdx.x;
+  unsigned tkey[kCountPer], slot[kCountPer], loc[kCountPer];
+  // every lane of a wave runs every iteration, so the cross-lane operations
+  // always see the full wave
+#pragma unroll
+  for (int j = 0; j < kCountPer; ++j) {
+    const int64_t i = base + (int64_t)j * kCountBlock;
     const bool valid = i < np;
-    unsigned key = 0xffffffffu;
+    unsigned key = kEmpty;
     if (valid) {
       const int tx = cell_of<FIXED>(pos, np, i, 0, logn) >> lx;
       const int ty = cell_of<FIXED>(pos, np, i, 1, logn) >> ly;
       const int tz = cell_of<FIXED>(pos, np, i, 2, logn) >> lz;
-      key = (unsigned)((tx * ty_n + ty) * tz_n + tz) * kSlices + (blockIdx.x % kSlices);
+      key = (unsigned)((tx * ty_n + ty) * tz_n + tz);
     }
     const unsigned prev = __shfl_up(key, 1, 64);
     const bool head = (lane == 0) || (prev != key);
@@ -63,95 +102,173 @@ __global__ void __launch_bounds__(kBlock) k_sort_count(const void* __restrict__ 
     const int leader = 63 - __clzll(heads & upto);
     const unsigned long long after = (lane == 63) ? 0ull : (heads & ~upto);
     const int next = after ? __ffsll((long long)after) - 1 : 64;
-    unsigned run_base = 0;
-    if (head && valid) run_base = atomicAdd(&counts[key], (unsigned)(next - lane));
-    run_base = __shfl(run_base, leader, 64);
-    if (valid) {
-      key_out[i] = key;
-      rank_out[i] = run_base + (unsigned)(lane - leader);
+    unsigned s = kEmpty, b = 0;
+    if (head && valid) {
+      s = hash_slot(hkey, key);
+      // a full table sends the run straight to the device counter
+      b = s != kEmpty ? atomicAdd(&hcnt[s], (unsigned)(next - lane))
+                      : atomicAdd(&cnt[key], (unsigned)(next - lane));
+    }
+    s = __shfl(s, leader, 64);
+    b = __shfl(b, leader, 64);
+    tkey[j] = key;
+    slot[j] = s;
+    loc[j] = b + (unsigned)(lane - leader);
+  }
+  __syncthreads();
+  // one device atomic per distinct tile of the block: the block's base rank
+  for (int i = threadIdx.x; i < kHash; i += kCountBlock) {
+    const unsigned k = hkey[i];
+    if (k != kEmpty) hcnt[i] = atomicAdd(&cnt[k], hcnt[i]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kCountPer; ++j) {
+    const int64_t i = base + (int64_t)j * kCountBlock;
+    if (i < np) {
+      key_out[i] = tkey[j] * kSlices + slice;
+      rank_out[i] = slot[j] != kEmpty ? hcnt[slot[j]] + loc[j] : loc[j];
     }
   }
 }
 
-// One block scans the sliced tile counts.  Thread k owns a contiguous run
-// of tiles; a tile's kSlices counters are read as four 16-byte vectors.  Two
-// exclusive prefix sums come out of one pass: particles per slice (and per
-// tile) and chunks per tile.
-constexpr int kScanThreads = 1024;
-static_assert(kSlices == 16, "the scan reads a tile's counters as four uint4");
-
-__device__ __forceinline__ void block_scan2(unsigned& a, unsigned& b, unsigned* pa,
-                                            unsigned* pb) {
-  // inclusive Hillis-Steele scan of (a, b) over the block, returns exclusive
-  pa[threadIdx.x] = a;
-  pb[threadIdx.x] = b;
-  __syncthreads();
-  for (int off = 1; off < kScanThreads; off <<= 1) {
-    const unsigned va = (int)threadIdx.x >= off ? pa[threadIdx.x - off] : 0u;
-    const unsigned vb = (int)threadIdx.x >= off ? pb[threadIdx.x - off] : 0u;
-    __syncthreads();
-    pa[threadIdx.x] += va;
-    pb[threadIdx.x] += vb;
-    __syncthreads();
+// Exclusive block-wide prefix sums of (a, b) over kScanBlock threads; also
+// returns the block totals.
+__device__ __forceinline__ void block_scan2(unsigned& a, unsigned& b, unsigned& ta,
+                                            unsigned& tb) {
+  __shared__ unsigned wa[kScanBlock / 64], wb[kScanBlock / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  unsigned ia = a, ib = b;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const unsigned va = __shfl_up(ia, off, 64), vb = __shfl_up(ib, off, 64);
+    if (lane >= off) {
+      ia += va;
+      ib += vb;
+    }
   }
-  a = threadIdx.x ? pa[threadIdx.x - 1] : 0u;
-  b = threadIdx.x ? pb[threadIdx.x - 1] : 0u;
+  if (lane == 63) {
+    wa[w] = ia;
+    wb[w] = ib;
+  }
+  __syncthreads();
+  unsigned pa = 0, pb = 0;
+  ta = tb = 0;
+#pragma unroll
+  for (int k = 0; k < kScanBlock / 64; ++k) {
+    if (k < w) {
+      pa += wa[k];
+      pb += wb[k];
+    }
+    ta += wa[k];
+    tb += wb[k];
+  }
+  a = pa + ia - a;
+  b = pb + ib - b;
+  __syncthreads();
 }
 
-__global__ void __launch_bounds__(kScanThreads) k_sort_scan(const unsigned* __restrict__ counts,
-                                                           int tiles,
-                                                           unsigned* __restrict__ slice_start,
-                                                           unsigned* __restrict__ tile_start,
-                                                           unsigned* __restrict__ chunk_start,
-                                                           Batch bt) {
+__device__ __forceinline__ unsigned tile_total(const unsigned* counts, int cstride, int t,
+                                               unsigned* sl) {
+  unsigned tot = 0;
+#pragma unroll
+  for (int s = 0; s < kSlices; ++s) {
+    const unsigned c = counts[(size_t)s * cstride + t];
+    if (sl) sl[s] = c;
+    tot += c;
+  }
+  return tot;
+}
+
+// Per block of kScanBlock tiles: particle and chunk totals.
+__global__ void __launch_bounds__(kScanBlock) k_sort_scan_reduce(const unsigned* __restrict__ counts,
+                                                                int tiles, int cstride,
+                                                                unsigned* __restrict__ sums,
+                                                                Batch bt) {
   {
     const int sl = bslot(bt);
     counts = woff(counts, bt, sl);
+    sums = woff(sums, bt, sl);
+  }
+  const int t = blockIdx.x * kScanBlock + threadIdx.x;
+  unsigned a = 0, b = 0;
+  if (t < tiles) {
+    a = tile_total(counts, cstride, t, nullptr);
+    b = (a + kChunk - 1) / kChunk;
+  }
+  unsigned ta, tb;
+  block_scan2(a, b, ta, tb);
+  if (threadIdx.x == 0) {
+    sums[2 * blockIdx.x] = ta;
+    sums[2 * blockIdx.x + 1] = tb;
+  }
+}
+
+// Down-sweep: offsets of the earlier blocks, then per-tile prefix sums.
+__global__ void __launch_bounds__(kScanBlock) k_sort_scan_down(const unsigned* __restrict__ counts,
+                                                              int tiles, int cstride,
+                                                              const unsigned* __restrict__ sums,
+                                                              unsigned* __restrict__ slice_start,
+                                                              unsigned* __restrict__ tile_start,
+                                                              unsigned* __restrict__ chunk_start,
+                                                              Batch bt) {
+  {
+    const int sl = bslot(bt);
+    counts = woff(counts, bt, sl);
+    sums = woff(sums, bt, sl);
     slice_start = woff(slice_start, bt, sl);
     tile_start = woff(tile_start, bt, sl);
     chunk_start = woff(chunk_start, bt, sl);
   }
-  __shared__ unsigned pa[kScanThreads], pb[kScanThreads];
-  const int per = (tiles + kScanThreads - 1) / kScanThreads;
-  const int lo = threadIdx.x * per;
-  const int hi = min(tiles, lo + per);
-  const uint4* c4 = reinterpret_cast<const uint4*>(counts);
-  unsigned sp = 0, sc = 0;
-  for (int t = lo; t < hi; ++t) {
-    unsigned tot = 0;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const uint4 c = c4[4 * t + v];
-      tot += c.x + c.y + c.z + c.w;
+  __shared__ unsigned off[2];
+  if (threadIdx.x < 64) {
+    unsigned pa = 0, pb = 0;
+    for (int k = threadIdx.x; k < (int)blockIdx.x; k += 64) {
+      pa += sums[2 * k];
+      pb += sums[2 * k + 1];
     }
-    sp += tot;
-    sc += (tot + kChunk - 1) / kChunk;
-  }
-  unsigned rp = sp, rc = sc;
-  block_scan2(rp, rc, pa, pb);
-  uint4* s4 = reinterpret_cast<uint4*>(slice_start);
-  for (int t = lo; t < hi; ++t) {
-    tile_start[t] = rp;
-    chunk_start[t] = rc;
-    unsigned tot = 0;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const uint4 c = c4[4 * t + v];
+    for (int o = 32; o > 0; o >>= 1) {
+      pa += __shfl_xor(pa, o, 64);
+      pb += __shfl_xor(pb, o, 64);
+    }
+    if (threadIdx.x == 0) {
+      off[0] = pa;
+      off[1] = pb;
+    }
+  }
+  __syncthreads();
+  const int t = blockIdx.x * kScanBlock + threadIdx.x;
+  unsigned c[kSlices];
+  unsigned a = 0, b = 0;
+  if (t < tiles) {
+    a = tile_total(counts, cstride, t, c);
+    b = (a + kChunk - 1) / kChunk;
+  }
+  unsigned ta, tb;
+  block_scan2(a, b, ta, tb);
+  a += off[0];
+  b += off[1];
+  if (t < tiles) {
+    tile_start[t] = a;
+    chunk_start[t] = b;
+    unsigned r = a;
+    uint4* s4 = reinterpret_cast<uint4*>(slice_start + (size_t)t * kSlices);
+#pragma unroll
+    for (int v = 0; v < kSlices / 4; ++v) {
       uint4 o;
-      o.x = rp;
-      o.y = o.x + c.x;
-      o.z = o.y + c.y;
-      o.w = o.z + c.z;
-      rp = o.w + c.w;
-      tot += c.x + c.y + c.z + c.w;
-      s4[4 * t + v] = o;
+      o.x = r;
+      o.y = o.x + c[4 * v];
+      o.z = o.y + c[4 * v + 1];
+      o.w = o.z + c[4 * v + 2];
+      r = o.w + c[4 * v + 3];
+      s4[v] = o;
     }
-    rc += (tot + kChunk - 1) / kChunk;
   }
-  if (threadIdx.x == kScanThreads - 1) {
-    slice_start[(size_t)tiles * kSlices] = rp;
-    tile_start[tiles] = rp;
-    chunk_start[tiles] = rc;
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+    slice_start[(size_t)tiles * kSlices] = off[0] + ta;
+    tile_start[tiles] = off[0] + ta;
+    chunk_start[tiles] = off[1] + tb;
   }
 }
 
@@ -193,20 +310,25 @@ static unsigned grid_p(int64_t np) {
 hipError_t launch_sort_count(bool fixed, const void* pos, int64_t np, int logn,
                              unsigned* counts, unsigned* key, unsigned* rank, hipStream_t s,
                              const Batch& bt) {
-  const dim3 g(grid_p(np), bt.count);
+  const int64_t per = (int64_t)kCountBlock * kCountPer;
+  const dim3 g((unsigned)(np > 0 ? (np + per - 1) / per : 1), bt.count);
+  const int cs = count_stride(tile_count(logn));
   if (fixed)
-    hipLaunchKernelGGL(k_sort_count<true>, g, dim3(kBlock), 0, s, pos, np, logn, counts, key,
-                       rank, bt);
+    hipLaunchKernelGGL(k_sort_count<true>, g, dim3(kCountBlock), 0, s, pos, np, logn, counts, cs,
+                       key, rank, bt);
   else
-    hipLaunchKernelGGL(k_sort_count<false>, g, dim3(kBlock), 0, s, pos, np, logn, counts, key,
-                       rank, bt);
+    hipLaunchKernelGGL(k_sort_count<false>, g, dim3(kCountBlock), 0, s, pos, np, logn, counts,
+                       cs, key, rank, bt);
   return hipGetLastError();
 }
 
-hipError_t launch_sort_scan(const unsigned* counts, int tiles, unsigned* slice_start,
-                            unsigned* tile_start, unsigned* chunk_start, hipStream_t s,
-                            const Batch& bt) {
-  hipLaunchKernelGGL(k_sort_scan, dim3(1, bt.count), dim3(kScanThreads), 0, s, counts, tiles,
+hipError_t launch_sort_scan(const unsigned* counts, int tiles, unsigned* sums,
+                            unsigned* slice_start, unsigned* tile_start, unsigned* chunk_start,
+                            hipStream_t s, const Batch& bt) {
+  const dim3 g(scan_blocks(tiles), bt.count);
+  const int cs = count_stride(tiles);
+  hipLaunchKernelGGL(k_sort_scan_reduce, g, dim3(kScanBlock), 0, s, counts, tiles, cs, sums, bt);
+  hipLaunchKernelGGL(k_sort_scan_down, g, dim3(kScanBlock), 0, s, counts, tiles, cs, sums,
                      slice_start, tile_start, chunk_start, bt);
   return hipGetLastError();
 }
