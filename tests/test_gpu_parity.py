@@ -463,3 +463,73 @@ def test_step_sort_every_flag(pm, gpu):
     b = v2.cpu().numpy().astype(np.float64)
     for k in (1, 2):
         assert abs((b ** k).sum() - (a ** k).sum()) < 1e-6 * np.abs(a ** k).sum()
+
+
+def _blob_state(n, frac=0.6, sigma=1.5, seed=21):
+    """A dense Gaussian blob (frac of the particles, width sigma cells) on a
+    uniform background: tiles of the blob hold many chunks of particles."""
+    rng = np.random.default_rng(seed)
+    npart = n ** 3
+    nb = int(frac * npart)
+    centre = np.array([n / 2 - 0.3, n / 4 + 0.2, n / 2 + 0.1])   # straddles tile faces
+    x = np.concatenate([centre + sigma * rng.standard_normal((nb, 3)),
+                        n * rng.random((npart - nb, 3))]) % n
+    v = 0.05 * rng.standard_normal((npart, 3))
+    return quantize_state(x, v, n, {"kind": "blob"})
+
+
+def _lex(pos, vel):
+    a = np.concatenate([pos.view(np.uint32).astype(np.float64), vel.astype(np.float64)], axis=0)
+    return a[:, np.lexsort(a[::-1])]
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_multi_chunk_tiles_deposit(pm, gpu, precision):
+    """Tiles holding many chunks (partial windows summed by the reduce
+    kernel) against the direct deposit of the same particles."""
+    import torch
+    n = 64
+    st = _blob_state(n)
+    lp, _ = cosmo_setup(n, 10.0, 1e-22, precision=precision)
+    fp32 = precision == 0
+    ctx_t = _ctx(pm, lp, gpu)
+    ctx_d = _ctx(pm, lp, gpu)
+    pos, vel = to_device(st, gpu, fp32_positions=fp32)
+    ctx_t.sort(pos, vel)
+    d_t = torch.empty(n ** 3, dtype=torch.float32, device=gpu)
+    d_d = torch.empty_like(d_t)
+    ctx_t.deposit(pos, d_t)
+    ctx_d.deposit(pos, d_d)
+    torch.cuda.synchronize()
+    # the blob's tiles really hold several chunks of 4096
+    cell = positions_cells(pos, n, fp32).astype(np.int64)
+    tile = ((cell[:, 0] >> 3) * (n // 8) + (cell[:, 1] >> 3)) * (n // 32) + (cell[:, 2] >> 5)
+    assert np.bincount(tile).max() > 4 * 4096
+    if precision == 1:
+        assert np.array_equal(mass_mesh(ctx_t), mass_mesh(ctx_d))
+        assert mass_mesh(ctx_t).sum() == st.npart * 2 ** 40
+    else:
+        # float atomics sum the blob's cells (thousands of particles each) in
+        # another order: rounding grows like sqrt(terms) * 6e-8
+        assert rel_l2(d_t.cpu().numpy(), d_d.cpu().numpy()) < 1e-5
+
+
+def test_multi_chunk_tiles_fused_steps(pm, gpu):
+    """Steps with a sort before every step (tiled gather with the fused
+    deposit over multi-chunk tiles) evolve bitwise the same particle set as
+    unsorted steps (direct gather and deposit)."""
+    import torch
+    n = 64
+    st = _blob_state(n, seed=22)
+    lp, _ = cosmo_setup(n, 10.0, 1e-22)
+    times = [0.5 * math.exp(0.01 * k) for k in range(4)]
+    c1 = _ctx(pm, lp, gpu)
+    p1, v1 = to_device(st, gpu)
+    c1.step(p1, v1, times)
+    c2 = _ctx(pm, lp, gpu)
+    p2, v2 = to_device(st, gpu)
+    c2.step(p2, v2, times, flags=pm.PM_SORT_EVERY(1))
+    torch.cuda.synchronize()
+    assert np.array_equal(mass_mesh(c1), mass_mesh(c2))
+    assert np.array_equal(_lex(p1.cpu().numpy(), v1.cpu().numpy()),
+                          _lex(p2.cpu().numpy(), v2.cpu().numpy()))
