@@ -227,7 +227,9 @@ pm_status pm_batch_workspace_bytes(const pm_params* params, int32_t slots, size_
 
 /* Create a batch on a caller-owned workspace (256-byte aligned) and stream.
  * All slots start with box = params->box and hbar_over_m =
- * params->hbar_over_m. */
+ * params->hbar_over_m.  The batch allocates two pinned host buffers (the
+ * per-call slot list and kick/drift table are staged through them, so a
+ * call never waits for steps still queued); PM_EDEVICE if that fails. */
 pm_status pm_batch_init(const pm_params* params, int32_t slots, void* d_workspace, size_t bytes,
                         void* hip_stream, pm_batch** out);
 
@@ -249,7 +251,8 @@ pm_status pm_batch_step(pm_batch* batch, void* d_pos, float* d_vel, int32_t nact
                         const int32_t* slots, const double* times, int32_t nsteps,
                         int32_t flags);
 
-/* Free the host-side batch object. */
+/* Wait for the batch's queued uploads, then free its host-side object and
+ * pinned staging buffers (the caller's workspace is untouched). */
 pm_status pm_batch_destroy(pm_batch* batch);
 
 /* Free the host-side context (no device memory is owned). */
