@@ -89,7 +89,12 @@ def run_gpu(st, n, steps, warmup, a_start, kernel_pass=True, sort_every=10, fp32
     p0 = st.pos_f32 if fp32 else st.pos_fixed.view(np.int32)
     pos = torch.from_numpy(p0.copy()).to(dev)
     vel = torch.from_numpy(st.vel32.copy()).to(dev)
-    sort_flag = pm.PM_SORT_EVERY(sort_every) if sort_every else 0
+    # sort_every < 0: adaptive interval (PM_SORT_AUTO); 0: never; k: every k steps
+    # (the FP32 form has no adaptive interval: it sorts every 10 steps then)
+    if sort_every < 0:
+        sort_flag = pm.PM_SORT_EVERY(10) if fp32 else pm.PM_SORT_AUTO
+    else:
+        sort_flag = pm.PM_SORT_EVERY(sort_every) if sort_every else 0
     flags0 = 0
     if evolve_to is not None:
         k = max(1, int(round(math.log(evolve_to / a_start) / EVOLVE_DLNA)))
@@ -241,8 +246,9 @@ def main():
     ap.add_argument("--no-kernel-pass", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--sort-every", type=int, default=10,
-                    help="sort particles by tile every k steps inside the timed steps (0: never)")
+    ap.add_argument("--sort-every", type=int, default=-1,
+                    help="sort particles by tile every k steps inside the timed steps (0: never, "
+                         "-1: adaptive interval from sampled stray counts, the default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -287,7 +293,7 @@ def main():
             "a_start": 0.01,
             "dlna_per_step": DLNA,
             "event_ms_per_step": res["event_ms"] / args.steps,
-            "sort_every": args.sort_every,
+            "sort_every": "adaptive" if args.sort_every < 0 else args.sort_every,
         },
     }
     if "kernels" in res:

@@ -109,6 +109,14 @@ typedef struct pm_ctx pm_ctx;
  * then changes; use pm_sort with an id array between calls to track
  * particles. */
 #define PM_SORT_EVERY(k) ((((int32_t)(k)) & 0xffff) << 8)
+/* Sort by tile at an interval the context adapts to how fast particles
+ * leave their tiles (fixed-point form only; PM_EUNSUPPORTED otherwise).
+ * The context samples the count of particles whose deposit left their
+ * tile's window into pinned host memory (allocated on first use, freed by
+ * pm_destroy) and reads it once it has arrived, without waiting: the
+ * interval, and so the particle order, may depend on timing, never the
+ * state as a set of particles.  Overrides PM_SORT_EVERY. */
+#define PM_SORT_AUTO (1 << 24)
 
 /* Bytes of device workspace a context with these parameters needs.  Pure
  * host function, no device access.  Returns PM_EINVAL / PM_EUNSUPPORTED for

@@ -9,6 +9,7 @@ from ._lib import (  # noqa: F401
     PM_CONTINUE,
     PM_FIXED32,
     PM_FP32,
+    PM_SORT_AUTO,
     PM_SORT_EVERY,
     PMBatch,
     PMContext,

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libfdmpm.so")
 PM_OK, PM_EINVAL, PM_ENOMEM, PM_EDEVICE, PM_EUNSUPPORTED, PM_ESTATE = 0, -1, -2, -3, -4, -5
 PM_FP32, PM_FIXED32 = 0, 1
 PM_CONTINUE = 1
+PM_SORT_AUTO = 1 << 24
 
 
 def PM_SORT_EVERY(k: int) -> int:

@@ -80,6 +80,14 @@ struct pm_ctx {
   bool have_q;
   bool fields_at_pos;  // phi, q correspond to the positions left by pm_step
   Timer timer;
+  // adaptive sort interval (PM_SORT_AUTO): a sampled stray count of the
+  // fused deposit is copied to pinned memory and read once it has arrived
+  unsigned* h_stat = nullptr;   // kStraySlices * kStrayStride counters
+  hipEvent_t ev_stat = nullptr;
+  bool stat_pending = false;
+  int stat_age = 0;             // steps since the sort at the sampled step
+  int sort_interval = 10;
+  int since_sort = 1 << 30;     // steps since the last sort
 };
 
 
@@ -128,7 +136,7 @@ Layout layout_for(const pm_params& p) {
     off = align_up(off + bytes);
     return at;
   };
-  L.mass = take(8 * nc);
+  L.mass = take(8 * nc + kStrayBytes);   // mesh, then the stray counters
   L.delta = take(4 * nc);
   L.phi = take(4 * nc);
   L.q = take(4 * nc);
@@ -292,7 +300,7 @@ double midpoint(const pm_params& p, double t0, double t1) {
 
 // ------------------------------------------------------------ launch sequences
 pm_status run_deposit(pm_ctx* c, const void* pos) {
-  PM_TRY(timed(c, kcFill, [&] { return launch_fill_zero(c->mass, 8 * c->ncell, c->stream); }));
+  PM_TRY(timed(c, kcFill, [&] { return launch_fill_zero(c->mass, 8 * c->ncell + kStrayBytes, c->stream); }));
   return timed(c, kcDeposit, [&] {
     if (c->fixed && c->sorted)
       return launch_deposit_fixed_tiled(static_cast<const uint32_t*>(pos), c->np, c->logn,
@@ -530,12 +538,65 @@ pm_status pm_force(pm_ctx* c, const float* d_phi, const float* d_q, const void* 
   });
 }
 
+// Adaptive sort interval.  After a fused gather-deposit on a sorted context
+// the stray counters (particles whose deposit fell outside their tile's
+// window) are copied to pinned memory; once the copy has arrived (polled,
+// never waited for) the interval is set from the stray fraction f_k seen k
+// steps after a sort.  The window's halo absorbs small displacements, so
+// strays grow faster than linearly with the age of the sort; modelling
+// them as f_k (j/k)^2 at age j, a sort of cost C every L steps and strays
+// of cost c each cost C/L + c f_k L^2 / (3 k^2) per step, least at
+// L = (kSortBalance k^2 / f_k)^(1/3), with kSortBalance = 3 C / (2 c) in
+// units of strays amounting to all particles, tuned on evolved 256^3 boxes
+// (best L = 2 at a = 0.5; no strays at all at a = 0.01).
+namespace {
+
+constexpr double kSortBalance = 0.02;
+constexpr int kSortIntervalMax = 32;
+
+pm_status sample_sort_stat(pm_ctx* c) {
+  if (!c->sorted) return PM_OK;
+  if (!c->h_stat) {
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->h_stat), kStrayBytes) != hipSuccess) {
+      c->h_stat = nullptr;
+      return PM_EDEVICE;
+    }
+    if (hipEventCreateWithFlags(&c->ev_stat, hipEventDisableTiming) != hipSuccess)
+      return PM_EDEVICE;
+  }
+  PM_TRY(dev(hipMemcpyAsync(c->h_stat, static_cast<char*>(c->mass) + 8 * c->ncell, kStrayBytes,
+                            hipMemcpyDeviceToHost, c->stream)));
+  PM_TRY(dev(hipEventRecord(c->ev_stat, c->stream)));
+  c->stat_pending = true;
+  c->stat_age = c->since_sort;
+  return PM_OK;
+}
+
+void poll_sort_stat(pm_ctx* c) {
+  if (!c->stat_pending || hipEventQuery(c->ev_stat) != hipSuccess) return;
+  c->stat_pending = false;
+  double strays = 0.0;
+  for (int k = 0; k < kStraySlices; ++k) strays += c->h_stat[k * kStrayStride];
+  const double f = strays / (double)c->np;
+  const double k = c->stat_age > 0 ? c->stat_age : 1;
+  int interval = kSortIntervalMax;
+  if (f > 0.0) {
+    const double l = cbrt(kSortBalance * k * k / f);
+    interval = l < 1.0 ? 1 : (l > kSortIntervalMax ? kSortIntervalMax : (int)l);
+  }
+  c->sort_interval = interval;
+}
+
+}  // namespace
+
 pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int32_t nsteps,
                   int32_t flags) {
   if (!c || !d_pos || !d_vel || !times) return PM_EINVAL;
   if (nsteps < 1) return PM_EINVAL;
-  if (flags & ~(PM_CONTINUE | PM_SORT_EVERY(0xffff))) return PM_EINVAL;
+  if (flags & ~(PM_CONTINUE | PM_SORT_EVERY(0xffff) | PM_SORT_AUTO)) return PM_EINVAL;
   const int sort_every = (flags >> 8) & 0xffff;
+  const bool sort_auto = (flags & PM_SORT_AUTO) != 0;
+  if (sort_auto && c->p.precision != PM_FIXED32) return PM_EUNSUPPORTED;
   for (int s = 0; s <= nsteps; ++s) {
     if (!isfinite(times[s])) return PM_EINVAL;
     if (c->p.comoving && !(times[s] > 0.0)) return PM_EINVAL;
@@ -549,17 +610,25 @@ pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int
     const double t0 = times[s], t1 = times[s + 1];
     const double tm = midpoint(c->p, t0, t1);
     const Kick open = kick(c->p, t0, tm);
-    if (sort_every > 0 && s % sort_every == 0) PM_TRY(pm_sort(c, d_pos, d_vel, nullptr));
+    if (sort_auto) {
+      poll_sort_stat(c);
+      if (!c->sorted || c->since_sort >= c->sort_interval)
+        PM_TRY(pm_sort(c, d_pos, d_vel, nullptr));
+    } else if (sort_every > 0 && s % sort_every == 0) {
+      PM_TRY(pm_sort(c, d_pos, d_vel, nullptr));
+    }
     GatherConst gc;
     gc.fg = (float)(close.g + open.g);
     gc.fq = (float)(close.q + open.q);
     gc.fd_units = drift(c->p, t0, t1) * fdu;
     // gather + kick + drift, fused with the deposit of the drifted particles
-    PM_TRY(timed(c, kcFill, [&] { return launch_fill_zero(c->mass, 8 * c->ncell, c->stream); }));
+    PM_TRY(timed(c, kcFill, [&] { return launch_fill_zero(c->mass, 8 * c->ncell + kStrayBytes, c->stream); }));
     PM_TRY(timed(c, kcGatherKD, [&] {
       return launch_gather(c->fixed, c->has_q, true, c->logn, d_pos, d_vel, c->phi, c->q, c->np,
                            gc, c->sorted ? &c->tmap : nullptr, c->mass, c->stream);
     }));
+    ++c->since_sort;
+    if (sort_auto && !c->stat_pending) PM_TRY(sample_sort_stat(c));
     PM_TRY(run_fields(c, d_pos, false, false));
     close = kick(c->p, tm, t1);
   }
@@ -603,6 +672,7 @@ pm_status pm_sort(pm_ctx* c, void* d_pos, float* d_vel, int32_t* d_ids) {
     return e;
   }));
   c->sorted = true;
+  c->since_sort = 0;
   return PM_OK;
 }
 
@@ -843,7 +913,7 @@ pm_status pm_batch_step(pm_batch* b, void* d_pos, float* d_vel, int32_t nactive,
     return PM_OK;
   };
   if (!(flags & PM_CONTINUE)) {
-    PM_TRY(dev(launch_fill_zero(c->mass, 8 * c->ncell, c->stream, bt)));
+    PM_TRY(dev(launch_fill_zero(c->mass, 8 * c->ncell + kStrayBytes, c->stream, bt)));
     if (c->fixed)
       PM_TRY(dev(sorted ? launch_deposit_fixed_tiled(static_cast<const uint32_t*>(d_pos), c->np,
                                                      c->logn, c->tmap,
@@ -867,7 +937,7 @@ pm_status pm_batch_step(pm_batch* b, void* d_pos, float* d_vel, int32_t nactive,
   unused.fd_units = 0.0;
   for (int k = 0; k < nsteps; ++k) {
     if (sort_every > 0 && k % sort_every == 0) PM_TRY(sort_all());
-    PM_TRY(dev(launch_fill_zero(c->mass, 8 * c->ncell, c->stream, bt)));
+    PM_TRY(dev(launch_fill_zero(c->mass, 8 * c->ncell + kStrayBytes, c->stream, bt)));
     PM_TRY(dev(launch_gather(c->fixed, true, true, c->logn, d_pos, d_vel, c->phi, c->q, c->np,
                              unused, sorted ? &c->tmap : nullptr, c->mass, c->stream, row(k))));
     PM_TRY(fields(row(k)));
@@ -889,7 +959,9 @@ pm_status pm_batch_destroy(pm_batch* b) {
 
 pm_status pm_destroy(pm_ctx* c) {
   if (!c) return PM_EINVAL;
-  if (!c->timer.pending.empty()) (void)hipStreamSynchronize(c->stream);
+  if (!c->timer.pending.empty() || c->stat_pending) (void)hipStreamSynchronize(c->stream);
+  if (c->ev_stat) (void)hipEventDestroy(c->ev_stat);
+  if (c->h_stat) (void)hipHostFree(c->h_stat);
   for (auto& r : c->timer.pending) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);

@@ -95,7 +95,8 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiled(const void* __restrict
   constexpr int N = 1 << LOGN;
   constexpr int MASK = N - 1;
   constexpr int TX = 1 << tile_lx(LOGN), TY = 1 << tile_ly(LOGN), TZ = 1 << tile_lz(LOGN);
-  constexpr int WX = TX + 1, WY = TY + 1, WZ = TZ + 1;
+  constexpr int HD = kDepHalo;   // window: cells o - HD .. o + T + HD
+  constexpr int WX = TX + 1 + 2 * HD, WY = TY + 1 + 2 * HD, WZ = TZ + 1 + 2 * HD;
   constexpr int NTY = N / TY, NTZ = N / TZ;
   __shared__ T acc[WX * WY * WZ];
   const int sl = bslot(bt);
@@ -119,8 +120,8 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiled(const void* __restrict
       const float* p = static_cast<const float*>(pos);
       float_weights<LOGN>(p[i], p[np + i], p[2 * np + i], ix, iy, iz, w);
     }
-    const int rx = (ix - ox) & MASK, ry = (iy - oy) & MASK, rz = (iz - oz) & MASK;
-    if (rx < TX && ry < TY && rz < TZ) {
+    const int rx = (ix - ox + HD) & MASK, ry = (iy - oy + HD) & MASK, rz = (iz - oz + HD) & MASK;
+    if (rx < TX + 2 * HD && ry < TY + 2 * HD && rz < TZ + 2 * HD) {
 #pragma unroll
       for (int c = 0; c < 8; ++c)
         atomicAdd(&acc[((rx + (c >> 2)) * WY + ry + ((c >> 1) & 1)) * WZ + rz + (c & 1)], w[c]);
@@ -133,8 +134,8 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiled(const void* __restrict
     const T v = acc[c];
     if (v != (T)0) {
       const int lx = c / (WY * WZ), ly = (c / WZ) % WY, lz = c % WZ;
-      const size_t cell = ((size_t)((ox + lx) & MASK) * N + ((oy + ly) & MASK)) * N +
-                          ((oz + lz) & MASK);
+      const size_t cell = ((size_t)((ox - HD + lx) & MASK) * N + ((oy - HD + ly) & MASK)) * N +
+                          ((oz - HD + lz) & MASK);
       add_global(&mass[cell], v);
     }
   }

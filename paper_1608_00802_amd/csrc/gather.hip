@@ -223,19 +223,23 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather_tiled(void* __restrict_
   constexpr int N = 1 << LOGN;
   constexpr int MASK = N - 1;
   constexpr int TX = 1 << tile_lx(LOGN), TY = 1 << tile_ly(LOGN), TZ = 1 << tile_lz(LOGN);
-  constexpr int WX = TX + 3, WY = TY + 3, WZ = TZ + 3;
+  constexpr int HG = kGatherHalo, HD = kDepHalo;
+  // F window: cells o - 1 - HG .. o + T + 1 + HG; deposit window: o - HD .. o + T + HD
+  constexpr int WX = TX + 3 + 2 * HG, WY = TY + 3 + 2 * HG, WZ = TZ + 3 + 2 * HG;
   constexpr int NTY = N / TY, NTZ = N / TZ;
-  constexpr int DX = TX + 1, DY = TY + 1, DZ = TZ + 1;
+  constexpr int DX = TX + 1 + 2 * HD, DY = TY + 1 + 2 * HD, DZ = TZ + 1 + 2 * HD;
   __shared__ float win[WX * WY * WZ];
   __shared__ T dacc[DEP ? DX * DY * DZ : 1];
+  __shared__ unsigned n_stray;
   int t;
   unsigned lo, hi;
   if (!chunk_of(tm, t, lo, hi)) return;
+  if (threadIdx.x == 0) n_stray = 0;
   const int ox = (t / (NTY * NTZ)) * TX, oy = ((t / NTZ) % NTY) * TY, oz = (t % NTZ) * TZ;
   for (int c = threadIdx.x; c < WX * WY * WZ; c += kGatherBlock) {
     const int lx = c / (WY * WZ), ly = (c / WZ) % WY, lz = c % WZ;
-    const size_t idx = ((size_t)((ox - 1 + lx) & MASK) * N + ((oy - 1 + ly) & MASK)) * N +
-                       ((oz - 1 + lz) & MASK);
+    const size_t idx = ((size_t)((ox - 1 - HG + lx) & MASK) * N +
+                        ((oy - 1 - HG + ly) & MASK)) * N + ((oz - 1 - HG + lz) & MASK);
     win[c] = mesh_f<LOGN, HAS_Q>(phi, q, gc, idx);
   }
   if constexpr (DEP)
@@ -246,9 +250,10 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather_tiled(void* __restrict_
     float f[3], xf[3];
     uint32_t u[3];
     load_cell<LOGN, FIXED>(pos, np, p, ic, f, u, xf);
-    const int rx = (ic[0] - ox) & MASK, ry = (ic[1] - oy) & MASK, rz = (ic[2] - oz) & MASK;
+    const int rx = (ic[0] - ox + HG) & MASK, ry = (ic[1] - oy + HG) & MASK,
+              rz = (ic[2] - oz + HG) & MASK;
     float g[3];
-    if (rx < TX && ry < TY && rz < TZ) {
+    if (rx < TX + 2 * HG && ry < TY + 2 * HG && rz < TZ + 2 * HG) {
       interp_grad(f, [&](int a, int b, int c) {
         return win[((rx + a) * WY + ry + b) * WZ + rz + c];
       }, g);
@@ -266,25 +271,36 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather_tiled(void* __restrict_
       int jx, jy, jz;
       T w[8];
       new_weights<LOGN, FIXED>(unew, xnew, jx, jy, jz, w);
-      const int sx = (jx - ox) & MASK, sy = (jy - oy) & MASK, sz = (jz - oz) & MASK;
-      if (sx < TX && sy < TY && sz < TZ) {
+      const int sx = (jx - ox + HD) & MASK, sy = (jy - oy + HD) & MASK,
+                sz = (jz - oz + HD) & MASK;
+      const bool inside = sx < TX + 2 * HD && sy < TY + 2 * HD && sz < TZ + 2 * HD;
+      if (inside) {
 #pragma unroll
         for (int c = 0; c < 8; ++c)
           atomicAdd(&dacc[((sx + (c >> 2)) * DY + sy + ((c >> 1) & 1)) * DZ + sz + (c & 1)], w[c]);
       } else {
         deposit_global<LOGN>(static_cast<T*>(mass_v), jx, jy, jz, w);
       }
+      // count strays: one LDS atomic per wave
+      const unsigned long long m = __ballot(!inside);
+      if (m && (threadIdx.x & 63) == __ffsll((long long)__ballot(1)) - 1)
+        atomicAdd(&n_stray, (unsigned)__popcll(m));
     }
   }
   if constexpr (DEP) {
     __syncthreads();
     T* mass = static_cast<T*>(mass_v);
+    if (threadIdx.x == 0 && n_stray)
+      atomicAdd(reinterpret_cast<unsigned*>(reinterpret_cast<char*>(mass_v) +
+                                            8 * ((size_t)N * N * N)) +
+                    (blockIdx.x % kStraySlices) * kStrayStride,
+                n_stray);
     for (int c = threadIdx.x; c < DX * DY * DZ; c += kGatherBlock) {
       const T v = dacc[c];
       if (v != (T)0) {
         const int lx = c / (DY * DZ), ly = (c / DZ) % DY, lz = c % DZ;
-        const size_t cell = ((size_t)((ox + lx) & MASK) * N + ((oy + ly) & MASK)) * N +
-                            ((oz + lz) & MASK);
+        const size_t cell = ((size_t)((ox - HD + lx) & MASK) * N + ((oy - HD + ly) & MASK)) * N +
+                            ((oz - HD + lz) & MASK);
         add_global(&mass[cell], v);
       }
     }

@@ -41,6 +41,23 @@ constexpr int kMassShift = 40;            // one particle = 2^40 integer mass un
 #define FDM_TILE_LZ 5
 #endif
 constexpr int kTileLX = FDM_TILE_LX, kTileLY = FDM_TILE_LY, kTileLZ = FDM_TILE_LZ;
+// Halo cells around a tile in the LDS windows of the tiled gather (the
+// interpolation stencil of particles that drifted up to kGatherHalo cells
+// out of their tile is still in LDS) and of the tiled deposit (the same for
+// deposits that land up to kDepHalo cells out of the tile).
+#ifndef FDM_GATHER_HALO
+#define FDM_GATHER_HALO 0
+#endif
+#ifndef FDM_DEP_HALO
+#define FDM_DEP_HALO 1
+#endif
+constexpr int kGatherHalo = FDM_GATHER_HALO, kDepHalo = FDM_DEP_HALO;
+// The fused gather-deposit counts the particles whose deposit fell outside
+// their chunk's window ("strays") in kStraySlices counters, one 128-byte line
+// apart, stored right after the mass mesh (cleared with it every step).
+constexpr int kStraySlices = 16;
+constexpr int kStrayStride = 32;   // unsigned counters between slices
+constexpr size_t kStrayBytes = 4 * kStraySlices * kStrayStride;
 // A tile's particles are processed in chunks of at most kChunk per block, so
 // heavily populated tiles spread over many blocks.
 constexpr int kChunk = 4096;

@@ -369,10 +369,17 @@ class GpuExecutor:
                     any(p["runs"] or p["chunks"] for p in self.pools.values()))
 
     # -- work
-    def _flags(self, started):
+    def _flags(self, started, pooled=True):
+        """Pools sort every sort_every steps; a standalone run in fixed point
+        lets its context adapt the interval."""
         pm = self.pm
-        return (pm.PM_SORT_EVERY(self.sort_every) if self.sort_every else 0) | \
-            (pm.PM_CONTINUE if started else 0)
+        if not self.sort_every:
+            sort = 0
+        elif not pooled and self.fixed:
+            sort = pm.PM_SORT_AUTO
+        else:
+            sort = pm.PM_SORT_EVERY(self.sort_every)
+        return sort | (pm.PM_CONTINUE if started else 0)
 
     def advance(self, chunk):
         torch = self.torch
@@ -405,7 +412,7 @@ class GpuExecutor:
             while len(run["chunks"]) < self.inflight and run["k"] < len(run["times"]) - 1:
                 kk = min(chunk, len(run["times"]) - 1 - run["k"])
                 run["ctx"].step(run["pos"], run["vel"], run["times"][run["k"]: run["k"] + kk + 1],
-                                self._flags(run["started"]))
+                                self._flags(run["started"], pooled=False))
                 run["k"] += kk
                 run["started"] = True
                 ev = torch.cuda.Event()

@@ -30,6 +30,16 @@ def test_header_declarations_exported(lib):
         assert hasattr(lib, name), name
 
 
+def test_flag_values_match_header():
+    text = open(HEADER).read()
+    assert re.search(r"#define PM_CONTINUE 1\b", text)
+    assert re.search(r"#define PM_SORT_AUTO \(1 << 24\)", text)
+    assert _lib.PM_CONTINUE == 1 and _lib.PM_SORT_AUTO == 1 << 24
+    # PM_SORT_EVERY(k) occupies bits 8..23, clear of both single-bit flags
+    assert _lib.PM_SORT_EVERY(0xffff) == 0xffff << 8
+    assert _lib.PM_SORT_EVERY(0xffff) & (_lib.PM_CONTINUE | _lib.PM_SORT_AUTO) == 0
+
+
 def test_struct_layout_matches_header():
     # pm_params: int32, int32, int64, double, int32, int32, 7 doubles -> 88 bytes
     assert ctypes.sizeof(_lib.PMParams) == 88

@@ -533,3 +533,32 @@ def test_multi_chunk_tiles_fused_steps(pm, gpu):
     assert np.array_equal(mass_mesh(c1), mass_mesh(c2))
     assert np.array_equal(_lex(p1.cpu().numpy(), v1.cpu().numpy()),
                           _lex(p2.cpu().numpy(), v2.cpu().numpy()))
+
+
+def test_sort_auto_equals_unsorted(pm, gpu):
+    """PM_SORT_AUTO (sort interval chosen from sampled stray counts) evolves
+    bitwise the same particle set as unsorted steps, over calls that sort
+    at different ages; the FP32 form rejects it."""
+    import torch
+    n = 64
+    st = _blob_state(n, seed=23)
+    lp, _ = cosmo_setup(n, 10.0, 1e-22)
+    times = [0.5 * math.exp(0.02 * k) for k in range(13)]
+    c1 = _ctx(pm, lp, gpu)
+    p1, v1 = to_device(st, gpu)
+    # the same two calls (a call boundary splits the merged half-kicks)
+    c1.step(p1, v1, times[:5])
+    c1.step(p1, v1, times[4:], flags=pm.PM_CONTINUE)
+    c2 = _ctx(pm, lp, gpu)
+    p2, v2 = to_device(st, gpu)
+    c2.step(p2, v2, times[:5], flags=pm.PM_SORT_AUTO)
+    c2.step(p2, v2, times[4:], flags=pm.PM_SORT_AUTO | pm.PM_CONTINUE)
+    torch.cuda.synchronize()
+    assert np.array_equal(mass_mesh(c1), mass_mesh(c2))
+    assert np.array_equal(_lex(p1.cpu().numpy(), v1.cpu().numpy()),
+                          _lex(p2.cpu().numpy(), v2.cpu().numpy()))
+    lf, _ = cosmo_setup(n, 10.0, 1e-22, precision=0)
+    c3 = _ctx(pm, lf, gpu)
+    p3, v3 = to_device(st, gpu, fp32_positions=True)
+    with pytest.raises(pm.PMError):
+        c3.step(p3, v3, times[:3], flags=pm.PM_SORT_AUTO)
