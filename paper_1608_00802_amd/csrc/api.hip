@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "../../include/fdmpm.h"
@@ -589,6 +590,44 @@ void poll_sort_stat(pm_ctx* c) {
 
 }  // namespace
 
+namespace {
+
+// Count, scan and scatter the particles (and ids) into dst by tile; the
+// tile map then describes dst.
+pm_status sort_into(pm_ctx* c, const void* pos, const float* vel, const int32_t* ids,
+                    uint32_t* dst_pos, float* dst_vel, int* dst_ids) {
+  const size_t cbytes = 4 * (size_t)kSlices * count_stride(c->tiles);
+  PM_TRY(timed(c, kcFill, [&] { return launch_fill_zero(c->tile_counts, cbytes, c->stream); }));
+  PM_TRY(timed(c, kcSortCount, [&] {
+    return launch_sort_count(c->fixed, pos, c->np, c->logn, c->tile_counts, c->sort_key,
+                             c->sort_rank, c->stream);
+  }));
+  PM_TRY(timed(c, kcSortScan, [&] {
+    return launch_sort_scan(c->tile_counts, c->tiles, c->scan_sums, c->slice_start, c->tile_start,
+                            c->chunk_start, c->stream);
+  }));
+  PM_TRY(timed(c, kcSortScatter, [&] {
+    return launch_sort_scatter(pos, vel, ids, c->np, c->sort_key, c->sort_rank, c->slice_start,
+                               dst_pos, dst_vel, dst_ids, c->stream);
+  }));
+  c->sorted = true;
+  c->since_sort = 0;
+  return PM_OK;
+}
+
+pm_status copy_particles(pm_ctx* c, void* pos, float* vel, const void* src_pos,
+                         const float* src_vel) {
+  return timed(c, kcSortCopy, [&] {
+    hipError_t e = hipMemcpyAsync(pos, src_pos, 12 * (size_t)c->np, hipMemcpyDeviceToDevice,
+                                  c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(vel, src_vel, 12 * (size_t)c->np, hipMemcpyDeviceToDevice, c->stream);
+    return e;
+  });
+}
+
+}  // namespace
+
 pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int32_t nsteps,
                   int32_t flags) {
   if (!c || !d_pos || !d_vel || !times) return PM_EINVAL;
@@ -604,6 +643,20 @@ pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int
   }
   if (!((flags & PM_CONTINUE) && c->fields_at_pos)) PM_TRY(run_fields(c, d_pos, false));
   c->fields_at_pos = false;
+  // A sort scatters the particles into the other of two buffers (the
+  // caller's arrays and the workspace copies), which then becomes current;
+  // the caller's arrays receive the state once, at the end of the call.
+  void* cur_pos = d_pos;
+  float* cur_vel = d_vel;
+  void* alt_pos = c->pos_tmp;
+  float* alt_vel = c->vel_tmp;
+  auto sort_step = [&]() -> pm_status {
+    PM_TRY(sort_into(c, cur_pos, cur_vel, nullptr, static_cast<uint32_t*>(alt_pos), alt_vel,
+                     nullptr));
+    std::swap(cur_pos, alt_pos);
+    std::swap(cur_vel, alt_vel);
+    return PM_OK;
+  };
   const double fdu = c->fixed ? ldexp(1.0, c->B) : 1.0;
   Kick close = {0.0, 0.0};
   for (int s = 0; s < nsteps; ++s) {
@@ -612,10 +665,9 @@ pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int
     const Kick open = kick(c->p, t0, tm);
     if (sort_auto) {
       poll_sort_stat(c);
-      if (!c->sorted || c->since_sort >= c->sort_interval)
-        PM_TRY(pm_sort(c, d_pos, d_vel, nullptr));
+      if (!c->sorted || c->since_sort >= c->sort_interval) PM_TRY(sort_step());
     } else if (sort_every > 0 && s % sort_every == 0) {
-      PM_TRY(pm_sort(c, d_pos, d_vel, nullptr));
+      PM_TRY(sort_step());
     }
     GatherConst gc;
     gc.fg = (float)(close.g + open.g);
@@ -624,12 +676,12 @@ pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int
     // gather + kick + drift, fused with the deposit of the drifted particles
     PM_TRY(timed(c, kcFill, [&] { return launch_fill_zero(c->mass, 8 * c->ncell + kStrayBytes, c->stream); }));
     PM_TRY(timed(c, kcGatherKD, [&] {
-      return launch_gather(c->fixed, c->has_q, true, c->logn, d_pos, d_vel, c->phi, c->q, c->np,
-                           gc, c->sorted ? &c->tmap : nullptr, c->mass, c->stream);
+      return launch_gather(c->fixed, c->has_q, true, c->logn, cur_pos, cur_vel, c->phi, c->q,
+                           c->np, gc, c->sorted ? &c->tmap : nullptr, c->mass, c->stream);
     }));
     ++c->since_sort;
     if (sort_auto && !c->stat_pending) PM_TRY(sample_sort_stat(c));
-    PM_TRY(run_fields(c, d_pos, false, false));
+    PM_TRY(run_fields(c, cur_pos, false, false));
     close = kick(c->p, tm, t1);
   }
   GatherConst gc;
@@ -637,42 +689,23 @@ pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int
   gc.fq = (float)close.q;
   gc.fd_units = 0.0;
   PM_TRY(timed(c, kcKick, [&] {
-    return launch_gather(c->fixed, c->has_q, false, c->logn, d_pos, d_vel, c->phi, c->q, c->np,
-                         gc, c->sorted ? &c->tmap : nullptr, nullptr, c->stream);
+    return launch_gather(c->fixed, c->has_q, false, c->logn, cur_pos, cur_vel, c->phi, c->q,
+                         c->np, gc, c->sorted ? &c->tmap : nullptr, nullptr, c->stream);
   }));
+  if (cur_pos != d_pos) PM_TRY(copy_particles(c, d_pos, d_vel, cur_pos, cur_vel));
   c->fields_at_pos = true;
   return PM_OK;
 }
 
 pm_status pm_sort(pm_ctx* c, void* d_pos, float* d_vel, int32_t* d_ids) {
   if (!c || !d_pos || !d_vel) return PM_EINVAL;
-  const size_t cbytes = 4 * (size_t)kSlices * count_stride(c->tiles);
-  PM_TRY(timed(c, kcFill, [&] { return launch_fill_zero(c->tile_counts, cbytes, c->stream); }));
-  PM_TRY(timed(c, kcSortCount, [&] {
-    return launch_sort_count(c->fixed, d_pos, c->np, c->logn, c->tile_counts, c->sort_key,
-                             c->sort_rank, c->stream);
-  }));
-  PM_TRY(timed(c, kcSortScan, [&] {
-    return launch_sort_scan(c->tile_counts, c->tiles, c->scan_sums, c->slice_start, c->tile_start,
-                            c->chunk_start, c->stream);
-  }));
-  PM_TRY(timed(c, kcSortScatter, [&] {
-    return launch_sort_scatter(d_pos, d_vel, d_ids, c->np, c->sort_key, c->sort_rank,
-                               c->slice_start, c->pos_tmp, c->vel_tmp, c->ids_tmp, c->stream);
-  }));
-  PM_TRY(timed(c, kcSortCopy, [&] {
-    hipError_t e = hipMemcpyAsync(d_pos, c->pos_tmp, 12 * (size_t)c->np,
-                                  hipMemcpyDeviceToDevice, c->stream);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(d_vel, c->vel_tmp, 12 * (size_t)c->np, hipMemcpyDeviceToDevice,
-                         c->stream);
-    if (e == hipSuccess && d_ids)
-      e = hipMemcpyAsync(d_ids, c->ids_tmp, 4 * (size_t)c->np, hipMemcpyDeviceToDevice,
-                         c->stream);
-    return e;
-  }));
-  c->sorted = true;
-  c->since_sort = 0;
+  PM_TRY(sort_into(c, d_pos, d_vel, d_ids, c->pos_tmp, c->vel_tmp, c->ids_tmp));
+  PM_TRY(copy_particles(c, d_pos, d_vel, c->pos_tmp, c->vel_tmp));
+  if (d_ids)
+    PM_TRY(timed(c, kcSortCopy, [&] {
+      return hipMemcpyAsync(d_ids, c->ids_tmp, 4 * (size_t)c->np, hipMemcpyDeviceToDevice,
+                            c->stream);
+    }));
   return PM_OK;
 }
 
