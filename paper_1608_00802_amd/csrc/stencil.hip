@@ -114,7 +114,8 @@ __global__ void __launch_bounds__(kBlock) k_qpot(const float* __restrict__ delta
 // QX consecutive x-planes.  Each plane of s-values (with a one-cell y/z halo)
 // is loaded once into LDS; the x-neighbours stay in registers, so delta is
 // read about (QY+2)(QZ+2)/(QY QZ) times instead of once per stencil point.
-constexpr int QY = 8, QZ = 32, QX = 8;
+// The loads of plane x + 2 are issued before plane x is computed.
+constexpr int QY = 8, QZ = 32, QX = 16;
 static_assert(QY * QZ == kBlock, "one cell per thread and plane");
 
 template <bool FIXED>
@@ -145,41 +146,57 @@ __global__ void __launch_bounds__(kBlock) k_qpot_tiled(const float* __restrict__
   constexpr int N = 1 << LOGN;
   constexpr int MASK = N - 1;
   constexpr int PY = QY + 2, PZ = QZ + 2;
-  __shared__ float pl[PY * PZ];
+  constexpr int PER = (PY * PZ + kBlock - 1) / kBlock;   // plane values per thread
+  // two plane buffers: plane x + 1 is committed to one while plane x is read
+  // from the other, and plane x + 2 is already in flight in registers
+  __shared__ float pl[2][PY * PZ];
   const int nby = N / QY, nbz = N / QZ;
   const int b = (int)blockIdx.x;
   const int bz = b % nbz, by = (b / nbz) % nby, bx = b / (nbz * nby);
   const int y0 = by * QY, z0 = bz * QZ, x0 = bx * QX;
   const int ty = threadIdx.x / QZ, tz = threadIdx.x % QZ;
   const int y = y0 + ty, z = z0 + tz;
-  auto load_plane = [&](int x) {
+  float pre[PER];
+  auto fetch = [&](int x) {
     const size_t base = (size_t)(x & MASK) * N * N;
-    for (int c = threadIdx.x; c < PY * PZ; c += kBlock) {
-      const int ly = c / PZ, lz = c % PZ;
-      const int gy = (y0 - 1 + ly) & MASK, gz = (z0 - 1 + lz) & MASK;
-      pl[c] = s_of<FIXED>(delta[base + (size_t)gy * N + gz], qc);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int c = threadIdx.x + k * kBlock;
+      if (c < PY * PZ) {
+        const int ly = c / PZ, lz = c % PZ;
+        pre[k] = delta[base + (size_t)((y0 - 1 + ly) & MASK) * N + ((z0 - 1 + lz) & MASK)];
+      }
     }
   };
-  auto inplane = [&]() {
-    const int c = (ty + 1) * PZ + tz + 1;
-    return (pl[c - PZ] + pl[c + PZ]) + (pl[c - 1] + pl[c + 1]);
+  auto commit = [&](float* buf) {
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int c = threadIdx.x + k * kBlock;
+      if (c < PY * PZ) buf[c] = s_of<FIXED>(pre[k], qc);
+    }
+  };
+  const int cc = (ty + 1) * PZ + tz + 1;
+  auto inplane = [&](const float* buf) {
+    return (buf[cc - PZ] + buf[cc + PZ]) + (buf[cc - 1] + buf[cc + 1]);
   };
   const float sq_floor = sqrtf((float)qc.fp64_below) - 1.0f;  // s below which the FP64 path runs
   double wsum = 0.0, usum = 0.0;
   float s_prev = s_of<FIXED>(delta[((size_t)((x0 - 1) & MASK) * N + y) * N + z], qc);
-  load_plane(x0);
+  fetch(x0);
+  commit(pl[0]);
+  fetch(x0 + 1);
   __syncthreads();
-  float s_cur = pl[(ty + 1) * PZ + tz + 1];
-  float in_cur = inplane();
-  float sy_cur = pl[(ty + 2) * PZ + tz + 1], sz_cur = pl[(ty + 1) * PZ + tz + 2];
-  __syncthreads();
+  float s_cur = pl[0][cc];
+  float in_cur = inplane(pl[0]);
+  float sy_cur = pl[0][cc + PZ], sz_cur = pl[0][cc + 1];
   for (int x = x0; x < x0 + QX; ++x) {
-    load_plane(x + 1);
+    float* nb = pl[(x - x0 + 1) & 1];
+    commit(nb);                               // plane x + 1
+    if (x + 2 <= x0 + QX) fetch(x + 2);
     __syncthreads();
-    const float s_next = pl[(ty + 1) * PZ + tz + 1];
-    const float in_next = inplane();
-    const float sy_next = pl[(ty + 2) * PZ + tz + 1], sz_next = pl[(ty + 1) * PZ + tz + 2];
-    __syncthreads();
+    const float s_next = nb[cc];
+    const float in_next = inplane(nb);
+    const float sy_next = nb[cc + PZ], sz_next = nb[cc + 1];
     const size_t i = ((size_t)x * N + y) * N + z;
     const float lap = ((s_prev + s_next) + in_cur) - 6.0f * s_cur;
     float qv;
