@@ -61,16 +61,16 @@ def alg_bytes(n: int, npart: int) -> dict:
     }
 
 
-def make_state(n):
+def make_state(n, box):
     from synth import zeldovich_state
-    return zeldovich_state(n, 10.0, 0.01, seed=1, m_ev=1e-22)
+    return zeldovich_state(n, box, 0.01, seed=1, m_ev=1e-22)
 
 
 EVOLVE_DLNA = math.log(100.0) / 150.0
 
 
 def run_gpu(st, n, steps, warmup, a_start, kernel_pass=True, sort_every=10, fp32=False,
-            evolve_to=None):
+            evolve_to=None, box=10.0):
     """Time `steps` steps (after `warmup`) from a_start; with evolve_to, the
     state is first stepped (untimed) from a_start to evolve_to in steps of
     d ln a = ln(100)/150."""
@@ -81,8 +81,8 @@ def run_gpu(st, n, steps, warmup, a_start, kernel_pass=True, sort_every=10, fp32
     from synth import comoving_code_params
 
     dev = torch.device("cuda:0")
-    hm = comoving_code_params(10.0, n, 1e-22, 0.7)["hbar_m_cells"] * (10.0 / n) ** 2
-    lp = pm.make_params(n, st.npart, 10.0, precision=pm.PM_FP32 if fp32 else pm.PM_FIXED32,
+    hm = comoving_code_params(box, n, 1e-22, 0.7)["hbar_m_cells"] * (box / n) ** 2
+    lp = pm.make_params(n, st.npart, box, precision=pm.PM_FP32 if fp32 else pm.PM_FIXED32,
                         comoving=True, omega_m=0.3, omega_l=0.7, h0=1.0, hbar_over_m=hm,
                         rho_floor=1e-6, rho_fp64_below=1e-3)
     ctx = pm.PMContext(lp, device=dev)
@@ -186,11 +186,11 @@ def kernel_table(kern, n, npart):
     return rows
 
 
-def cpu_baseline(st, n):
+def cpu_baseline(st, n, box):
     """FP64 oracle, one steady-state kick-drift-kick step on the full workload."""
     import oracle
     from synth import comoving_code_params
-    hm = comoving_code_params(10.0, n, 1e-22, 0.7)["hbar_m_cells"]
+    hm = comoving_code_params(box, n, 1e-22, 0.7)["hbar_m_cells"]
     p = oracle.Params(n=n, box=float(n), S=1.5 * 0.3, hbar_m=hm, comoving=True,
                       omega_m=0.3, omega_l=0.7, h0=1.0, rho_floor=1e-6)
     a0 = 0.01
@@ -238,6 +238,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--box", type=float, default=10.0, help="box side in Mpc/h")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-evolved", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
@@ -256,7 +257,7 @@ def main():
         sys.exit(2)
     n = args.n
     # host-side inputs first, before this process touches the GPU
-    st = make_state(n)
+    st = make_state(n, args.box)
     trace = ics = None
     if not args.no_serve:
         from paper_1608_00802_amd import serve
@@ -269,7 +270,7 @@ def main():
     if args.copy_calibration:
         copy_calibration()
     res = run_gpu(st, n, args.steps, args.warmup, 0.01, kernel_pass=not args.no_kernel_pass,
-                  sort_every=args.sort_every)
+                  sort_every=args.sort_every, box=args.box)
     value = res["np"] * args.steps / res["wall_s"]
     line = {
         "metric": METRIC,
@@ -285,7 +286,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic: Zel'dovich initial conditions from a seeded Gaussian field",
         "config": {
-            "workload": f"comoving 10 Mpc/h box, {n}^3 particles on a {n}^3 mesh, "
+            "workload": f"comoving {args.box:g} Mpc/h box, {n}^3 particles on a {n}^3 mesh, "
                         "m = 1e-22 eV, Omega_m = 0.3, h = 0.7, Zel'dovich ICs at a = 0.01, "
                         "fixed-point uint32 positions, FP32 FFT/stencils, int64 deposit",
             "n_mesh": n,
@@ -314,7 +315,7 @@ def main():
         line["step_alg_GBs"] = round(step_bytes / (res["wall_s"] / args.steps) / 1e9, 1)
     if not args.no_fp32:
         rf = run_gpu(st, n, args.steps, args.warmup, 0.01, kernel_pass=False,
-                     sort_every=args.sort_every, fp32=True)
+                     sort_every=args.sort_every, fp32=True, box=args.box)
         vf = rf["np"] * args.steps / rf["wall_s"]
         line["plain_fp32"] = {
             "form": "float32 positions, float atomics deposit, same FFT/stencil/gather kernels",
@@ -324,7 +325,7 @@ def main():
                         "(rel-L2 < 1e-5 on rho, phi, Q; tests/test_gpu_parity.py)"}
     if not args.no_evolved:
         re_ = run_gpu(st, n, args.steps, args.warmup, 0.01, kernel_pass=not args.no_kernel_pass,
-                      sort_every=args.sort_every, evolve_to=0.5)
+                      sort_every=args.sort_every, evolve_to=0.5, box=args.box)
         line["evolved"] = {
             "state": f"the same box stepped from a = 0.01 to a = 0.5 "
                      f"({re_['evolve_steps']} steps, untimed), then timed: nonlinear, clustered",
@@ -338,7 +339,7 @@ def main():
         line["serving"] = serve_section(trace, ics)
         del ics
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(st, n)
+        line["cpu_baseline"] = cpu_baseline(st, n, args.box)
     line["finite"] = res["finite"]
     print(json.dumps(line), flush=True)
 
