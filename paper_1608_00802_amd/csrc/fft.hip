@@ -122,12 +122,31 @@ __device__ __forceinline__ void fft_rows(float2* __restrict__ buf, const float2*
   }
 }
 
+#ifndef FDM_FFT_Z_ELEMS
+#define FDM_FFT_Z_ELEMS 4096
+#endif
+#ifndef FDM_FFT_Y_ELEMS
+#define FDM_FFT_Y_ELEMS 2048
+#endif
+#ifndef FDM_FFT_X_ELEMS
+#define FDM_FFT_X_ELEMS 2048
+#endif
+#ifndef FDM_FFT_X_MINCOL
+#define FDM_FFT_X_MINCOL 8
+#endif
+// Rows (complex elements / N) per block of each pass, and at least
+// FDM_FFT_X_MINCOL consecutive y columns (64-byte segments) per x-pass
+// block.  Small tiles leave room for four or more blocks per CU, so one
+// block's transform overlaps another's loads (256^3: 30 us less per step
+// than tiles twice as large).
 template <int N>
 struct Tiles {
   static constexpr int H = N / 2;
-  static constexpr int TZ = (8192 / N < N) ? 8192 / N : N;   // rows per z-pass block
-  static constexpr int TY = (4096 / N < N) ? 4096 / N : N;   // rows per y-pass block
-  static constexpr int TC = (4096 / N >= 16) ? ((4096 / N < N) ? 4096 / N : N) : 16;  // x-pass columns
+  static constexpr int ZE = FDM_FFT_Z_ELEMS, YE = FDM_FFT_Y_ELEMS, XE = FDM_FFT_X_ELEMS;
+  static constexpr int MC = FDM_FFT_X_MINCOL;
+  static constexpr int TZ = (ZE / N < N) ? ZE / N : N;   // rows per z-pass block
+  static constexpr int TY = (YE / N < N) ? YE / N : N;   // rows per y-pass block
+  static constexpr int TC = (XE / N >= MC) ? ((XE / N < N) ? XE / N : N) : MC;  // x-pass columns
 };
 
 // ---------------------------------------------------------------- pass 1
