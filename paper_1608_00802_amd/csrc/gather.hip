@@ -25,24 +25,36 @@ namespace fdm {
 
 enum GatherMode : int { kKick = 0, kKickDrift = 1, kForce = 2 };
 
-// Position of particle p: integer cell and fraction along each axis.
+// Position of one particle from its three 32-bit position words (fixed-point
+// units, or float bits): integer cell and fraction along each axis.
 template <int LOGN, bool FIXED>
-__device__ __forceinline__ void load_cell(const void* __restrict__ pos, int64_t np, int64_t p,
-                                          int ic[3], float f[3], uint32_t u[3], float xf[3]) {
+__device__ __forceinline__ void decode_cell(const uint32_t raw[3], int ic[3], float f[3],
+                                            uint32_t u[3], float xf[3]) {
   constexpr int MASK = (1 << LOGN) - 1;
   constexpr int B = 32 - LOGN;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     if constexpr (FIXED) {
-      u[d] = static_cast<const uint32_t*>(pos)[d * np + p];
+      u[d] = raw[d];
       ic[d] = (int)(u[d] >> B);
       f[d] = (float)(u[d] & ((1u << B) - 1u)) * (1.0f / (float)(1u << B));
     } else {
-      xf[d] = static_cast<const float*>(pos)[d * np + p];
+      xf[d] = __uint_as_float(raw[d]);
       const float fl = floorf(xf[d]);
       f[d] = xf[d] - fl;
       ic[d] = (int)fl & MASK;
     }
+  }
+}
+
+// The position words and velocity of particle p.
+__device__ __forceinline__ void load_particle(const void* __restrict__ pos,
+                                              const float* __restrict__ vel, int64_t np,
+                                              int64_t p, uint32_t raw[3], float v[3]) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    raw[d] = static_cast<const uint32_t*>(pos)[d * np + p];
+    v[d] = vel ? vel[d * np + p] : 0.0f;
   }
 }
 
@@ -95,8 +107,9 @@ __device__ __forceinline__ void interp_grad(const float f[3], At&& at, float g[3
 template <int LOGN, bool FIXED, int MODE>
 __device__ __forceinline__ void push(void* __restrict__ pos, float* __restrict__ vel,
                                      float* __restrict__ acc, int64_t np, int64_t p,
-                                     const float g[3], const uint32_t u[3], const float xf[3],
-                                     double fd_units, uint32_t unew[3], float xnew[3]) {
+                                     const float g[3], const float vin[3], const uint32_t u[3],
+                                     const float xf[3], double fd_units, uint32_t unew[3],
+                                     float xnew[3]) {
   constexpr int N = 1 << LOGN;
   if constexpr (MODE == kForce) {
 #pragma unroll
@@ -104,7 +117,7 @@ __device__ __forceinline__ void push(void* __restrict__ pos, float* __restrict__
   } else {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const float v = vel[d * np + p] + g[d];
+      const float v = vin[d] + g[d];
       vel[d * np + p] = v;
       if constexpr (MODE == kKickDrift) {
         if constexpr (FIXED) {
@@ -169,9 +182,10 @@ __global__ void __launch_bounds__(kBlock) k_gather(void* __restrict__ pos,
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += stride) {
     int ic[3];
-    float f[3], xf[3];
-    uint32_t u[3];
-    load_cell<LOGN, FIXED>(pos, np, p, ic, f, u, xf);
+    float f[3], xf[3], vin[3];
+    uint32_t u[3], raw[3];
+    load_particle(pos, MODE == kForce ? nullptr : vel, np, p, raw, vin);
+    decode_cell<LOGN, FIXED>(raw, ic, f, u, xf);
     float g[3];
     interp_grad(f, [&](int a, int b, int c) {
       const size_t idx = ((size_t)((ic[0] + a - 1) & MASK) * N + ((ic[1] + b - 1) & MASK)) * N +
@@ -180,7 +194,7 @@ __global__ void __launch_bounds__(kBlock) k_gather(void* __restrict__ pos,
     }, g);
     uint32_t unew[3];
     float xnew[3];
-    push<LOGN, FIXED, MODE>(pos, vel, acc, np, p, g, u, xf, gc.fd_units, unew, xnew);
+    push<LOGN, FIXED, MODE>(pos, vel, acc, np, p, g, vin, u, xf, gc.fd_units, unew, xnew);
     if constexpr (DEP) {
       int jx, jy, jz;
       T w[8];
@@ -235,6 +249,16 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather_tiled(void* __restrict_
   unsigned lo, hi;
   if (!chunk_of(tm, t, lo, hi)) return;
   if (threadIdx.x == 0) n_stray = 0;
+  // the first particles' loads are in flight while the window is staged;
+  // afterwards particle p + PF * kGatherBlock is loaded while p is processed
+  constexpr int PF = kGatherPrefetch;
+  uint32_t raw_n[PF][3];
+  float vin_n[PF][3];
+#pragma unroll
+  for (int k = 0; k < PF; ++k) {
+    const unsigned pk = lo + threadIdx.x + k * kGatherBlock;
+    if (pk < hi) load_particle(pos, vel, np, pk, raw_n[k], vin_n[k]);
+  }
   const int ox = (t / (NTY * NTZ)) * TX, oy = ((t / NTZ) % NTY) * TY, oz = (t % NTZ) * TZ;
   for (int c = threadIdx.x; c < WX * WY * WZ; c += kGatherBlock) {
     const int lx = c / (WY * WZ), ly = (c / WZ) % WY, lz = c % WZ;
@@ -247,9 +271,23 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather_tiled(void* __restrict_
   __syncthreads();
   for (unsigned p = lo + threadIdx.x; p < hi; p += kGatherBlock) {
     int ic[3];
-    float f[3], xf[3];
-    uint32_t u[3];
-    load_cell<LOGN, FIXED>(pos, np, p, ic, f, u, xf);
+    float f[3], xf[3], vin[3];
+    uint32_t u[3], raw[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      raw[d] = raw_n[0][d];
+      vin[d] = vin_n[0][d];
+    }
+#pragma unroll
+    for (int k = 0; k + 1 < PF; ++k)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        raw_n[k][d] = raw_n[k + 1][d];
+        vin_n[k][d] = vin_n[k + 1][d];
+      }
+    if (p + PF * kGatherBlock < hi)
+      load_particle(pos, vel, np, p + PF * kGatherBlock, raw_n[PF - 1], vin_n[PF - 1]);
+    decode_cell<LOGN, FIXED>(raw, ic, f, u, xf);
     const int rx = (ic[0] - ox + HG) & MASK, ry = (ic[1] - oy + HG) & MASK,
               rz = (ic[2] - oz + HG) & MASK;
     float g[3];
@@ -266,7 +304,7 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather_tiled(void* __restrict_
     }
     uint32_t unew[3];
     float xnew[3];
-    push<LOGN, FIXED, MODE>(pos, vel, acc, np, p, g, u, xf, gc.fd_units, unew, xnew);
+    push<LOGN, FIXED, MODE>(pos, vel, acc, np, p, g, vin, u, xf, gc.fd_units, unew, xnew);
     if constexpr (DEP) {
       int jx, jy, jz;
       T w[8];

@@ -27,6 +27,12 @@ constexpr int kBlock = 256;               // threads per block of the streaming 
 #define FDM_GATHER_BLOCK 512
 #endif
 constexpr int kGatherBlock = FDM_GATHER_BLOCK;  // threads per block of the tiled gather
+#ifndef FDM_GATHER_PREFETCH
+#define FDM_GATHER_PREFETCH 1
+#endif
+// Particles whose loads a tiled-gather thread keeps in flight ahead of the
+// one it processes.
+constexpr int kGatherPrefetch = FDM_GATHER_PREFETCH;
 constexpr int kMassShift = 40;            // one particle = 2^40 integer mass units
 
 // Particle tiles of the sort, the tiled deposit and the tiled gather:
