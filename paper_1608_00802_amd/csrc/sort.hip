@@ -302,7 +302,7 @@ __global__ void __launch_bounds__(kBlock) k_sort_scatter(
 
 static unsigned grid_p(int64_t np) {
   int64_t b = (np + kBlock - 1) / kBlock;
-  if (b > 16384) b = 16384;
+  if (b > 262144) b = 262144;   // up to one particle per thread at 256^3
   if (b < 1) b = 1;
   return (unsigned)b;
 }

@@ -57,7 +57,7 @@ def cosmo_setup(n, box_mpch, m_ev, h=0.7, om=0.3, precision=1, rho_fp64_below=1e
     return lp, op
 
 
-def c0_setup(precision=1):
+def single_mode_setup(precision=1):
     """Static box of the single-mode test: L = 1, 4 pi G rho = 1, hbar/m at
     half the quantum Jeans wavenumber of mode 2 (Eq. (19))."""
     from paper_1608_00802_amd import make_params

@@ -13,8 +13,8 @@ import pytest
 import oracle
 from synth import lattice_cells, sine_mode_state, to_fixed, quantize_state, zeldovich_state
 
-from gpu_helpers import (TWO40, c0_setup, cosmo_setup, mass_mesh, periodic_diff,
-                         positions_cells, rel_l2, to_device)
+from gpu_helpers import (TWO40, cosmo_setup, mass_mesh, periodic_diff, positions_cells, rel_l2,
+                         single_mode_setup, to_device)
 
 pytestmark = pytest.mark.gpu
 
@@ -240,10 +240,10 @@ def test_step_continue_equals_single_call(pm, gpu):
 # ------------------------------------------------------------------ static box, 100 steps
 
 @pytest.mark.parametrize("precision", [1, 0])
-def test_c0_drift_100_steps(pm, gpu, precision):
+def test_single_mode_drift_100_steps(pm, gpu, precision):
     import torch
     st = sine_mode_state(32, 2, 1e-3)
-    lp, op = c0_setup(precision)
+    lp, op = single_mode_setup(precision)
     ctx = _ctx(pm, lp, gpu)
     fp32 = precision == 0
     pos, vel = to_device(st, gpu, fp32_positions=fp32)
@@ -264,7 +264,7 @@ def test_c0_drift_100_steps(pm, gpu, precision):
     amp0 = periodic_diff(x0[:, 0], q[:, 0], 32) @ basis / (basis @ basis)
     if precision == 1:
         assert abs(amp / amp0 - 1.486711) < 1e-4
-    print(f"c0 precision={precision}: drift vs oracle {drift:.3e} cell, growth {amp / amp0:.7f}")
+    print(f"single mode precision={precision}: drift vs oracle {drift:.3e} cell, growth {amp / amp0:.7f}")
 
 
 # ------------------------------------------------------------------ energies
