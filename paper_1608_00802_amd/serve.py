@@ -19,10 +19,15 @@ Time to result runs from the request's arrival to the moment its state is
 on the host.
 
 Each run takes its own time steps: a Zel'dovich start at a = 0.01, uniform
-steps in ln a towards a = 1, each shortened where needed to keep the
-fastest linear quantum-pressure mode stable (omega_max dt <= c_q), and at
-most the requested number of steps -- so a run with a light boson in a
-small box stops short of a = 1 and reports where it stopped.
+steps in ln a towards a = 1, each shortened where needed so that no particle
+moves more than c_x cells and the fastest linear quantum-pressure mode stays
+stable (omega_max dt <= c_q), and at most the requested number of steps --
+so a run in a small box or with a light boson stops short of a = 1 and
+reports where it stopped.  The displacement bound needs the run's largest
+velocity: it is reduced on the device after every chunk of steps, and chunk
+j is planned with the value after chunk j - 2 (the newest one that has
+always arrived when chunk j is issued), so a run's steps depend on its own
+state only, never on what else is being served.
 
 The scheduling logic is independent of the executor: ``FakeExecutor`` runs
 it on a virtual clock without a GPU.
@@ -72,6 +77,7 @@ class Result:
     finished: float
     pos: object = None  # host arrays [3, Np] when the executor keeps results
     vel: object = None
+    times: list = None  # the scale factors of the run's steps
 
     @property
     def latency(self) -> float:
@@ -103,29 +109,46 @@ def hbar_over_m(m_ev: float, h: float = LITTLE_H) -> float:
     return hbar_ev_s * c_kms ** 2 / m_ev / mpc_km * h / 100.0
 
 
-def schedule(req: Request, omega_m: float = OMEGA_M, c_q: float = 0.5) -> list:
-    """Scale factors a_0 = 0.01 < a_1 < ... of the run's steps.
-
-    d ln a is ln(100)/nsteps, shortened to c_q H(a) / omega_max(a) where the
-    quantum-pressure bound is tighter (taken at the start of the step, where
-    it is tightest within the step: omega_max dt falls like a^-1/2 in the
-    matter era); the run ends at a = 1 or after nsteps steps.
-    """
+def dlna_step(req: Request, a: float, vmax: float = 0.0, omega_m: float = OMEGA_M,
+              c_q: float = 0.5, c_x: float = 1.0) -> float:
+    """d ln a of the step starting at scale factor a (Sec. II A time-step
+    condition: no particle moves more than a cell): ln(100)/nsteps,
+    shortened so that a particle of canonical momentum vmax (cells H0) moves
+    at most c_x cells (dx/dt = p/a^2, dt = d ln a / H) and so that
+    omega_max dt <= c_q.  Both bounds are taken at the start of the step,
+    where they are tightest within it in the matter era."""
     dx = req.box / req.n
     hm = hbar_over_m(req.m_ev) / (dx * dx)          # cells^2 H0
-    dmax = math.log(A_END / A_START) / req.nsteps
-    a = [A_START]
-    while len(a) <= req.nsteps and a[-1] < A_END:
-        ak = a[-1]
-        hub = math.sqrt(omega_m / ak ** 3 + 1.0 - omega_m)
-        d = dmax
-        if hm > 0:
-            d = min(d, c_q * hub * ak * ak / (OMEGA_MAX_COEF * hm))
-        nxt = ak * math.exp(d)
+    hub = math.sqrt(omega_m / a ** 3 + 1.0 - omega_m)
+    d = math.log(A_END / A_START) / req.nsteps
+    if hm > 0:
+        d = min(d, c_q * hub * a * a / (OMEGA_MAX_COEF * hm))
+    if vmax > 0:
+        d = min(d, c_x * a * a * hub / vmax)
+    return d
+
+
+def extend_times(req: Request, times: list, count: int, vmax: float = 0.0) -> int:
+    """Append up to count scale factors to the run's schedule `times`
+    (starting [0.01]), stopping at a = 1 or after nsteps steps; returns how
+    many were added."""
+    added = 0
+    while added < count and len(times) <= req.nsteps and times[-1] < A_END:
+        a = times[-1]
+        nxt = a * math.exp(dlna_step(req, a, vmax))
         if nxt >= A_END * (1.0 - 1e-12):
             nxt = A_END
-        a.append(nxt)
-    return a
+        times.append(nxt)
+        added += 1
+    return added
+
+
+def schedule(req: Request, vmax: float = 0.0) -> list:
+    """The whole schedule for a fixed velocity bound vmax (0: the quantum
+    pressure and step-count bounds only)."""
+    times = [A_START]
+    extend_times(req, times, req.nsteps, vmax)
+    return times
 
 
 def footprint_bytes(n: int, precision: int | None = None) -> int:
@@ -141,9 +164,9 @@ class Scheduler:
     """First-come-first-served admission, chunked advancement, completion.
 
     The executor interface: ``fits(req)`` (could it ever run),
-    ``can_admit(req)`` (can it start now), ``admit(req, state, times,
-    arrival, now)``, ``advance(chunk) -> bool`` (whether new work was
-    queued), ``poll(now) -> [Result]`` and ``busy()``.
+    ``can_admit(req)`` (can it start now), ``admit(req, state, arrival,
+    now)``, ``advance(chunk) -> bool`` (whether new work was queued),
+    ``poll(now) -> [Result]`` and ``busy()``.
     """
 
     def __init__(self, executor, chunk: int = 10):
@@ -186,7 +209,7 @@ class Scheduler:
                 queue.remove(req)
                 ta = now()
                 try:
-                    self.ex.admit(req, ics(req), schedule(req), req.arrival / time_scale, ta)
+                    self.ex.admit(req, ics(req), req.arrival / time_scale, ta)
                     self.events.append((ta, "admit", req.rid))
                 except MemoryError:
                     self.results[req.rid] = Result(req.rid, "failed", 0, A_START,
@@ -245,7 +268,8 @@ class GpuExecutor:
 
     def __init__(self, device="cuda:0", batch_max_n: int = 64, pool_slots=None,
                  budget_bytes: int | None = None, max_large: int = 4, inflight: int = 2,
-                 sort_every: int = 10, precision: int | None = None, keep_results: bool = False):
+                 sort_every: int = 10, precision: int | None = None, keep_results: bool = False,
+                 vmax_safety: float = 2.0):
         import torch
 
         from . import _lib as pm
@@ -264,6 +288,7 @@ class GpuExecutor:
         self.inflight = inflight
         self.sort_every = sort_every
         self.keep_results = keep_results
+        self.vmax_safety = vmax_safety
         self.upload_stream = torch.cuda.Stream(self.device)
         self.copy_stream = torch.cuda.Stream(self.device)
         self.free_streams = []
@@ -340,14 +365,16 @@ class GpuExecutor:
             t.record_stream(stream)
         return out
 
-    def admit(self, req, state, times, arrival, now):
+    def admit(self, req, state, arrival, now):
         torch, pm = self.torch, self.pm
-        run = {"req": req, "times": times, "k": 0, "arrival": arrival, "admitted": now,
-               "started": False}
+        pos_np, vel_np = state[0], state[1]
+        vm_ic = float(state[2]) if len(state) > 2 else float(np.abs(vel_np).max())
+        run = {"req": req, "times": [A_START], "k": 0, "arrival": arrival, "admitted": now,
+               "started": False, "issued_all": False, "vm_ic": vm_ic, "vm_after": []}
         hm = hbar_over_m(req.m_ev)
         if self._pooled(req.n):
             pool = self.pools.get(req.n) or self._new_pool(req.n)
-            pos, vel = self._upload(state, pool["stream"])
+            pos, vel = self._upload((pos_np, vel_np), pool["stream"])
             slot = pool["free"].pop(0)
             pool["batch"].load(slot, pos, vel, req.box, hm)
             run["slot"] = slot
@@ -358,11 +385,29 @@ class GpuExecutor:
                            omega_m=OMEGA_M, omega_l=1.0 - OMEGA_M, h0=1.0, hbar_over_m=hm)
         with torch.cuda.stream(stream):
             ctx = pm.PMContext(p, device=self.device, stream=stream)
-        pos, vel = self._upload(state, stream)
+        pos, vel = self._upload((pos_np, vel_np), stream)
         run.update(ctx=ctx, pos=pos, vel=vel, stream=stream, chunks=deque(),
                    bytes=self._run_bytes(req.n))
         self.used += run["bytes"]
         self.large.append(run)
+
+    def _plan(self, run, chunk):
+        """Extend the run's schedule by its next chunk; returns the steps.
+        Chunk j is planned with the run's largest velocity after chunk j - 2
+        (its reduction has always completed by the time chunk j is issued:
+        at most two chunks are queued), times a safety factor for the
+        growth since."""
+        j = len(run["vm_after"])
+        if j < 2:
+            v = run["vm_ic"]
+        else:
+            ev, host, idx = run["vm_after"][j - 2]
+            ev.synchronize()
+            v = float(host[idx])
+        kk = extend_times(run["req"], run["times"], chunk, self.vmax_safety * v)
+        run["issued_all"] = (run["times"][-1] >= A_END or
+                             len(run["times"]) - 1 >= run["req"].nsteps)
+        return kk
 
     def busy(self):
         return bool(self.large or self.copies or
@@ -386,13 +431,13 @@ class GpuExecutor:
         progressed = False
         for pool in self.pools.values():
             while len(pool["chunks"]) < self.inflight:
-                ready = [r for r in pool["runs"].values() if r["k"] < len(r["times"]) - 1]
+                ready = [r for r in pool["runs"].values() if not r["issued_all"]]
                 if not ready:
                     break
                 # one call per (first call or not, step count) group
                 groups = {}
                 for r in ready:
-                    kk = min(chunk, len(r["times"]) - 1 - r["k"])
+                    kk = self._plan(r, chunk)
                     groups.setdefault((r["started"], kk), []).append(r)
                 finishing = []
                 for (started, kk), runs in groups.items():
@@ -402,23 +447,35 @@ class GpuExecutor:
                     for r in runs:
                         r["k"] += kk
                         r["started"] = True
-                        if r["k"] == len(r["times"]) - 1:
+                        if r["issued_all"]:
                             finishing.append(r)
-                ev = torch.cuda.Event()
-                ev.record(pool["stream"])
+                # every slot's largest velocity, for planning later chunks
+                b = pool["batch"]
+                with torch.cuda.stream(pool["stream"]):
+                    vm = b.vel.abs().amax(dim=2).amax(dim=1)
+                    host = torch.empty(vm.shape, dtype=vm.dtype, pin_memory=True)
+                    host.copy_(vm, non_blocking=True)
+                    ev = torch.cuda.Event()
+                    ev.record(pool["stream"])
+                for r in ready:
+                    r["vm_after"].append((ev, host, r["slot"]))
                 pool["chunks"].append(_Chunk(ev, finishing))
                 progressed = True
         for run in self.large:
-            while len(run["chunks"]) < self.inflight and run["k"] < len(run["times"]) - 1:
-                kk = min(chunk, len(run["times"]) - 1 - run["k"])
+            while len(run["chunks"]) < self.inflight and not run["issued_all"]:
+                kk = self._plan(run, chunk)
                 run["ctx"].step(run["pos"], run["vel"], run["times"][run["k"]: run["k"] + kk + 1],
                                 self._flags(run["started"], pooled=False))
                 run["k"] += kk
                 run["started"] = True
-                ev = torch.cuda.Event()
-                ev.record(run["stream"])
-                done = run["k"] == len(run["times"]) - 1
-                run["chunks"].append(_Chunk(ev, [run] if done else []))
+                with torch.cuda.stream(run["stream"]):
+                    vm = run["vel"].abs().amax().reshape(1)
+                    host = torch.empty(1, dtype=vm.dtype, pin_memory=True)
+                    host.copy_(vm, non_blocking=True)
+                    ev = torch.cuda.Event()
+                    ev.record(run["stream"])
+                run["vm_after"].append((ev, host, 0))
+                run["chunks"].append(_Chunk(ev, [run] if run["issued_all"] else []))
                 progressed = True
         return progressed
 
@@ -474,7 +531,9 @@ class GpuExecutor:
             keep = ok and self.keep_results
             out.append(Result(req.rid, "ok" if ok else "failed", len(run["times"]) - 1,
                               run["times"][-1], run["arrival"], run["admitted"], now(),
-                              hp.numpy() if keep else None, hv.numpy() if keep else None))
+                              hp.numpy() if keep else None, hv.numpy() if keep else None,
+                              list(run["times"])))
+            run["vm_after"] = []
             release()
         self.copies = still
         return out
@@ -564,7 +623,8 @@ class FakeExecutor:
                 self.used -= self.pools.pop(n)["bytes"]
         return self.used + self.run_bytes(req.n) <= self.budget
 
-    def admit(self, req, state, times, arrival, now):
+    def admit(self, req, state, arrival, now):
+        times = schedule(req)
         if req.rid in self.oom:
             raise MemoryError(f"request {req.rid}: injected allocation failure")
         run = {"req": req, "times": times, "k": 0, "arrival": arrival, "admitted": now,
@@ -625,7 +685,7 @@ class FakeExecutor:
         if ok and self.compute is not None:
             pos, vel = self.compute(req, r["state"], r["times"])
         return Result(req.rid, "ok" if ok else "failed", len(r["times"]) - 1, r["times"][-1],
-                      r["arrival"], r["admitted"], now(), pos, vel)
+                      r["arrival"], r["admitted"], now(), pos, vel, list(r["times"]))
 
     def poll(self, now):
         t = self.clock()
@@ -648,13 +708,14 @@ class FakeExecutor:
 # ------------------------------------------------------------------ client side
 
 def make_ic(n, box, m_ev, seed, fp32=False):
-    """Zel'dovich initial state of one request: (positions, velocities),
-    [3, Np] each; positions fixed point (int32 bit patterns) or float32
-    cells."""
+    """Zel'dovich initial state of one request: (positions, velocities,
+    largest velocity component), arrays [3, Np]; positions fixed point
+    (int32 bit patterns) or float32 cells."""
     from synth import zeldovich_state
     st = zeldovich_state(n, box, A_START, seed, m_ev=m_ev, om=OMEGA_M, h=LITTLE_H)
     pos = st.pos_f32 if fp32 else np.ascontiguousarray(st.pos_fixed.view(np.int32))
-    return pos, np.ascontiguousarray(st.vel32)
+    vel = np.ascontiguousarray(st.vel32)
+    return pos, vel, float(np.abs(vel).max())
 
 
 def _make_ic_job(job):
@@ -680,8 +741,8 @@ def fp32_ics(ics: dict, trace) -> dict:
     the plain FP32 form)."""
     from synth import State
     by_id = {r.rid: r for r in trace}
-    return {rid: (State(by_id[rid].n, pos.view(np.uint32), vel, {}).pos_f32, vel)
-            for rid, (pos, vel) in ics.items()}
+    return {rid: (State(by_id[rid].n, pos.view(np.uint32), vel, {}).pos_f32, vel, vm)
+            for rid, (pos, vel, vm) in ics.items()}
 
 
 def serve_trace(trace, ics, executor, time_scale=1.0, chunk=10):

@@ -8,8 +8,8 @@ import numpy as np
 
 import oracle
 from paper_1608_00802_amd.serve import (A_END, A_START, OMEGA_MAX_COEF, FakeExecutor, Request,
-                                        Scheduler, VirtualClock, hbar_over_m, make_trace,
-                                        schedule, summarize)
+                                        Scheduler, VirtualClock, dlna_step, extend_times,
+                                        hbar_over_m, make_trace, schedule, summarize)
 from synth import comoving_code_params, zeldovich_state
 
 
@@ -71,6 +71,25 @@ def test_schedule_clamped_stops_short_and_is_stable():
         # omega_max dt <= 0.5, dt = d ln a / H, with the oracle's omega_max
         assert oracle.omega_max(p, a0) * math.log(a1 / a0) / hub <= 0.5 * (1 + 1e-9)
     assert abs(OMEGA_MAX_COEF * hm / oracle.omega_max(p, 1.0) - 1) < 1e-4
+
+
+def test_displacement_bound_and_chunked_schedule():
+    """With a velocity bound no particle moves more than a cell per step;
+    planning chunk by chunk with the same bound gives the same schedule as
+    planning it whole."""
+    r = _req(0, n=128, box=2.0, m_ev=1e-21, nsteps=200)
+    vmax = 3.0                                           # cells * H0, canonical momentum
+    a = np.array(schedule(r, vmax))
+    for a0, a1 in zip(a[:-1], a[1:]):
+        hub = math.sqrt(0.3 / a0 ** 3 + 0.7)
+        # displacement vmax / a^2 * dt, dt = d ln a / H
+        assert vmax / a0 ** 2 * math.log(a1 / a0) / hub <= 1.0 * (1 + 1e-9)
+    assert a[-1] < schedule(r)[-1]                        # a tighter bound gets less far
+    times = [A_START]
+    while extend_times(r, times, 7, vmax):
+        pass
+    assert times == list(a)
+    assert dlna_step(r, 0.5, 0.0) == math.log(100.0) / 200
 
 
 def test_schedule_short_only_where_the_bound_binds():
