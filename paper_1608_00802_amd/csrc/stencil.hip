@@ -150,71 +150,120 @@ __global__ void __launch_bounds__(kBlock) k_qpot_tiled(const float* __restrict__
   // two plane buffers: plane x + 1 is committed to one while plane x is read
   // from the other, and plane x + 2 is already in flight in registers
   __shared__ float pl[2][PY * PZ];
+  // FP64 sqrt(R) of one plane from the exact integer mass, built only where
+  // this plane or the next holds a near-empty cell, so the in-plane values of
+  // a near-empty region are computed once per cell
+  __shared__ double dpl[FIXED ? PY * PZ : 1];
+  // per wave: whether the committed plane holds a near-empty cell (two slots,
+  // alternating by plane)
+  __shared__ uint32_t nflag[2][kBlock / 64];
   const int nby = N / QY, nbz = N / QZ;
   const int b = (int)blockIdx.x;
   const int bz = b % nbz, by = (b / nbz) % nby, bx = b / (nbz * nby);
   const int y0 = by * QY, z0 = bz * QZ, x0 = bx * QX;
   const int ty = threadIdx.x / QZ, tz = threadIdx.x % QZ;
   const int y = y0 + ty, z = z0 + tz;
+  const float sq_floor = sqrtf((float)qc.fp64_below) - 1.0f;
+  const float near = sq_floor + 1e-6f;            // s below which a cell takes the FP64 path
+  const bool use64 = FIXED && qc.fp64_below > 0.0;
   float pre[PER];
+  auto plane_index = [&](int x, int c) {
+    const int ly = c / PZ, lz = c % PZ;
+    return (size_t)(x & MASK) * N * N + (size_t)((y0 - 1 + ly) & MASK) * N +
+           ((z0 - 1 + lz) & MASK);
+  };
   auto fetch = [&](int x) {
-    const size_t base = (size_t)(x & MASK) * N * N;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int c = threadIdx.x + k * kBlock;
+      if (c < PY * PZ) pre[k] = delta[plane_index(x, c)];
+    }
+  };
+  // s-values of the fetched plane into buf; records whether any is near empty
+  auto commit = [&](float* buf, int slot) {
+    bool any = false;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
       const int c = threadIdx.x + k * kBlock;
       if (c < PY * PZ) {
-        const int ly = c / PZ, lz = c % PZ;
-        pre[k] = delta[base + (size_t)((y0 - 1 + ly) & MASK) * N + ((z0 - 1 + lz) & MASK)];
+        const float sv = s_of<FIXED>(pre[k], qc);
+        buf[c] = sv;
+        any = any || sv < near;
       }
     }
-  };
-  auto commit = [&](float* buf) {
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const int c = threadIdx.x + k * kBlock;
-      if (c < PY * PZ) buf[c] = s_of<FIXED>(pre[k], qc);
+    if (use64) {
+      const bool wave_any = __any(any);
+      if (threadIdx.x % 64 == 0) nflag[slot][threadIdx.x / 64] = wave_any;
     }
+  };
+  // after the barrier that follows commit(.., slot)
+  auto plane_near = [&](int slot) {
+    if (!use64) return false;
+    uint32_t f = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) f |= nflag[slot][w];
+    return f != 0;
+  };
+  auto sd = [&](size_t j) {
+    double r = (double)mass[j] * qc.inv_mbar;
+    r = r > qc.floor_d ? r : qc.floor_d;
+    return sqrt(r);
   };
   const int cc = (ty + 1) * PZ + tz + 1;
   auto inplane = [&](const float* buf) {
     return (buf[cc - PZ] + buf[cc + PZ]) + (buf[cc - 1] + buf[cc + 1]);
   };
-  const float sq_floor = sqrtf((float)qc.fp64_below) - 1.0f;  // s below which the FP64 path runs
   double wsum = 0.0, usum = 0.0;
   float s_prev = s_of<FIXED>(delta[((size_t)((x0 - 1) & MASK) * N + y) * N + z], qc);
   fetch(x0);
-  commit(pl[0]);
+  commit(pl[0], 0);
   fetch(x0 + 1);
   __syncthreads();
+  bool near_cur = plane_near(0);                  // plane x holds a near-empty cell
   float s_cur = pl[0][cc];
   float in_cur = inplane(pl[0]);
   float sy_cur = pl[0][cc + PZ], sz_cur = pl[0][cc + 1];
+  double d_prev = 0.0;                            // FP64 sqrt(R) of plane x - 1, own column
   for (int x = x0; x < x0 + QX; ++x) {
-    float* nb = pl[(x - x0 + 1) & 1];
-    commit(nb);                               // plane x + 1
+    const int nbi = (x - x0 + 1) & 1;
+    float* nb = pl[nbi];
+    commit(nb, nbi);                          // plane x + 1
     if (x + 2 <= x0 + QX) fetch(x + 2);
     __syncthreads();
+    const bool near_next = plane_near(nbi);
     const float s_next = nb[cc];
     const float in_next = inplane(nb);
     const float sy_next = nb[cc + PZ], sz_next = nb[cc + 1];
+    // FP64 values of plane x: needed by its own near-empty cells and, as the
+    // x - 1 neighbour, by those of plane x + 1 (block-uniform condition)
+    double d_c = 0.0, d_ym = 0.0, d_yp = 0.0, d_zm = 0.0, d_zp = 0.0;
+    if constexpr (FIXED) {
+      if (near_cur || near_next) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+          const int c = threadIdx.x + k * kBlock;
+          if (c < PY * PZ) dpl[c] = sd(plane_index(x, c));
+        }
+        __syncthreads();
+        d_c = dpl[cc];
+        d_ym = dpl[cc - PZ];
+        d_yp = dpl[cc + PZ];
+        d_zm = dpl[cc - 1];
+        d_zp = dpl[cc + 1];
+      }
+    }
     const size_t i = ((size_t)x * N + y) * N + z;
     const float lap = ((s_prev + s_next) + in_cur) - 6.0f * s_cur;
     float qv;
     if constexpr (FIXED) {
       qv = qc.coef * lap / (1.0f + s_cur);
-      if (qc.fp64_below > 0.0 && s_cur < sq_floor + 1e-6f) {
+      if (use64 && s_cur < near) {
         // near-empty cell: sqrt(R) and Q in FP64 from the exact integer mass
-        auto sd = [&](int xx, int yy, int zz) {
-          const size_t j = ((size_t)(xx & MASK) * N + (yy & MASK)) * N + (zz & MASK);
-          double r = (double)mass[j] * qc.inv_mbar;
-          r = r > qc.floor_d ? r : qc.floor_d;
-          return sqrt(r);
-        };
-        const double c0 = sd(x, y, z);
+        const double c0 = d_c;
         if (c0 * c0 < qc.fp64_below) {
-          const double lapd = ((sd(x + 1, y, z) + sd(x - 1, y, z)) +
-                               (sd(x, y + 1, z) + sd(x, y - 1, z)) +
-                               (sd(x, y, z + 1) + sd(x, y, z - 1))) - 6.0 * c0;
+          if (x == x0) d_prev = sd(((size_t)((x0 - 1) & MASK) * N + y) * N + z);
+          const double d_next = sd(((size_t)((x + 1) & MASK) * N + y) * N + z);
+          const double lapd = ((d_next + d_prev) + (d_yp + d_ym) + (d_zp + d_zm)) - 6.0 * c0;
           qv = (float)(qc.coef_d * lapd / c0);
         }
       }
@@ -233,6 +282,8 @@ __global__ void __launch_bounds__(kBlock) k_qpot_tiled(const float* __restrict__
     in_cur = in_next;
     sy_cur = sy_next;
     sz_cur = sz_next;
+    d_prev = d_c;
+    near_cur = near_next;
   }
   if constexpr (ENERGY) {
     __shared__ double red[kBlock / 64];
