@@ -105,7 +105,11 @@ typedef struct pm_ctx pm_ctx;
                           on this context, with unchanged positions): skip
                           the opening force evaluation */
 /* Sort the particles by tile (as pm_sort, without ids) before every k-th
- * step of the call, starting with the first; k in 1..65535.  Particle order
+ * step of the call, starting with the first; k in 1..65535.  A sort is
+ * skipped when the particles have not moved since the last one.  A
+ * fixed-point context that has never sorted sorts before the opening force
+ * evaluation as well, with this flag or PM_SORT_AUTO, so that its deposit
+ * runs from tiles.  Particle order
  * then changes; use pm_sort with an id array between calls to track
  * particles. */
 #define PM_SORT_EVERY(k) ((((int32_t)(k)) & 0xffff) << 8)

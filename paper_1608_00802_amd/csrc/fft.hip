@@ -252,8 +252,9 @@ __global__ void __launch_bounds__(kBlock) k_fft_x_green(float2* __restrict__ spe
   __shared__ float2 tws[N];
   __shared__ float s2s[N];
   const int tid = threadIdx.x;
-  const int kz = blockIdx.x / (N / TC);
-  const int y0 = (blockIdx.x % (N / TC)) * TC;
+  const int b = (int)xcd_block(blockIdx.x, gridDim.x, xcd_group(FDM_XCD_FFTX, gridDim.x));
+  const int kz = b / (N / TC);
+  const int y0 = (b % (N / TC)) * TC;
   for (int k = tid; k < N; k += kBlock) {
     tws[k] = tw[k];
     s2s[k] = s2[k];

@@ -66,7 +66,10 @@ constexpr int kStrayStride = 32;   // unsigned counters between slices
 constexpr size_t kStrayBytes = 4 * kStraySlices * kStrayStride;
 // A tile's particles are processed in chunks of at most kChunk per block, so
 // heavily populated tiles spread over many blocks.
-constexpr int kChunk = 4096;
+#ifndef FDM_CHUNK
+#define FDM_CHUNK 8192
+#endif
+constexpr int kChunk = FDM_CHUNK;
 // The sort counts each tile in kSlices sub-counters (chosen by block) to
 // spread same-address atomics on densely populated tiles.
 constexpr int kSlices = 16;
@@ -82,6 +85,37 @@ __host__ __device__ constexpr int tile_lz(int logn) { return logn < kTileLZ ? lo
 __host__ __device__ constexpr int tile_count(int logn) {
   return (1 << (logn - tile_lx(logn))) * (1 << (logn - tile_ly(logn))) *
          (1 << (logn - tile_lz(logn)));
+}
+
+// Workgroups of a launch go to the eight XCDs in turn (workgroup b to XCD
+// b mod 8), each XCD with its own L2.  xcd_block renumbers them so that each
+// XCD takes `group` consecutive logical blocks per round: blocks that share
+// halo cells or cache lines then share an L2 and run at about the same time.
+// A bijection on [0, used); blocks from the last whole round on keep their
+// number (also those >= used).  group 0 leaves the numbering alone.
+constexpr unsigned kXcds = 8;
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned used, unsigned group) {
+  if (group == 0) return b;
+  const unsigned span = kXcds * group;
+  if (b >= used / span * span) return b;
+  const unsigned r = b % span;
+  return b - r + (r % kXcds) * group + r / kXcds;
+}
+// x-pass FFT blocks two at a time (the two halves of each 128-byte line of a
+// column run), tiled launches eight chunks at a time (a row of tiles along z
+// at N = 256: their windows share halo lines).  Measured at 256^3: 5 us less
+// per x-pass, 4-6 us less per gather; one contiguous run per XCD made the
+// gather of a clustered state 15% slower (uneven work per XCD) and the Q
+// stencil 8% slower.
+#ifndef FDM_XCD_FFTX
+#define FDM_XCD_FFTX 2        // -1: one contiguous run per XCD, else group size (0: off)
+#endif
+#ifndef FDM_XCD_TILES
+#define FDM_XCD_TILES 8
+#endif
+// group size for `used` blocks from one of the settings above
+__device__ __forceinline__ unsigned xcd_group(int setting, unsigned used) {
+  return setting < 0 ? used / kXcds : (unsigned)setting;
 }
 
 // Per-slot constants of a batched launch (runs of one mesh size stepping
@@ -171,10 +205,12 @@ inline unsigned tiled_grid(int64_t np, int tiles) {
 __device__ __forceinline__ bool chunk_of(const TileMap& tm, int& tile, unsigned& lo,
                                          unsigned& hi) {
   __shared__ int s_tile;
-  const unsigned b = blockIdx.x;
+  __shared__ unsigned s_chunk;
   if (threadIdx.x == 0) {
+    const unsigned used = tm.chunk_start[tm.tiles];
+    const unsigned b = xcd_block(blockIdx.x, used, xcd_group(FDM_XCD_TILES, used));
     int t = -1;
-    if (b < tm.chunk_start[tm.tiles]) {
+    if (b < used) {
       int l = 0, r = tm.tiles;  // first index with chunk_start > b lies in (l, r]
       while (r - l > 1) {
         const int m = (l + r) >> 1;
@@ -183,11 +219,12 @@ __device__ __forceinline__ bool chunk_of(const TileMap& tm, int& tile, unsigned&
       t = l;
     }
     s_tile = t;
+    s_chunk = b;
   }
   __syncthreads();
   tile = s_tile;
   if (tile < 0) return false;
-  const unsigned j = b - tm.chunk_start[tile];
+  const unsigned j = s_chunk - tm.chunk_start[tile];
   lo = tm.start[tile] + j * (unsigned)kChunk;
   const unsigned end = tm.start[tile + 1];
   hi = lo + (unsigned)kChunk < end ? lo + (unsigned)kChunk : end;
