@@ -33,15 +33,20 @@ HBM_PEAK_GBS = 8000.0
 DLNA = math.log(100.0) / 500.0
 
 
-def alg_bytes(n: int, npart: int) -> dict:
-    """Algorithmic HBM bytes per launch of each kernel family (fixed form).
+def alg_bytes(n: int, npart: int, steps: int = 20) -> dict:
+    """Algorithmic HBM bytes per launch of each kernel family (fixed form),
+    averaged over the launches of one continued call of `steps` steps.
 
     cells: N^3; spectrum: (N/2+1) N^2 complex64.  Each byte that a kernel
     must read or write once: positions 12 B/particle (uint32 x3), velocities
-    12 B/particle, int64 mass 8 B/cell, float meshes 4 B/cell.
+    12 B/particle, int64 mass 8 B/cell, float meshes 4 B/cell.  Inside a call
+    the Q stencil reads delta and phi and writes psi = F_g phi + F_q Q, and
+    the next gather reads psi alone; the last stencil launch of a call writes
+    Q and the first gather of a continued call reads phi and Q.
     """
     cells = n ** 3
     spec = 8 * (n // 2 + 1) * n * n
+    k = max(1, steps)
     return {
         "fill_zero": 8 * cells,
         "deposit": 12 * npart + 16 * cells,         # read positions, read+write mass once
@@ -50,10 +55,12 @@ def alg_bytes(n: int, npart: int) -> dict:
         "fft_x_green": 2 * spec,
         "fft_y_inv": 2 * spec,
         "c2r_z": spec + 4 * cells,
-        "qpot": 8 * cells,                           # delta in, Q out
-        # pos+vel in/out, phi and Q once, and the fused deposit of the drifted
-        # particles (read+write of the int64 mass mesh once)
-        "gather_kick_drift": 48 * npart + 8 * cells + 16 * cells,
+        # delta and phi in, psi out (k - 1 launches); delta in, Q out (one)
+        "qpot": (12 * (k - 1) + 8) * cells // k,
+        # pos+vel in/out, psi once (phi and Q in the first launch), and the
+        # fused deposit of the drifted particles (read+write of the int64
+        # mass mesh once)
+        "gather_kick_drift": 48 * npart + (4 * (k - 1) + 8) * cells // k + 16 * cells,
         "kick": 36 * npart + 8 * cells,
         "sort_count": 12 * npart + 8 * npart,        # positions in, key and rank out
         "sort_scatter": 8 * npart + 48 * npart,      # key, rank, pos+vel in, copies out
@@ -173,8 +180,8 @@ def measured_traffic(kernel: str, n: int):
     return int(k["fetch_bytes"] + k["write_bytes"])
 
 
-def kernel_table(kern, n, npart):
-    ab = alg_bytes(n, npart)
+def kernel_table(kern, n, npart, steps):
+    ab = alg_bytes(n, npart, steps)
     rows = {}
     for name, (launches, ms) in kern.items():
         avg = ms / launches
@@ -298,7 +305,7 @@ def main():
         },
     }
     if "kernels" in res:
-        table = kernel_table(res["kernels"], n, res["np"])
+        table = kernel_table(res["kernels"], n, res["np"], args.steps)
         line["kernels"] = table
         timed = {k: v for k, v in table.items() if "alg_bytes" in v}
         dom = max(timed, key=lambda k: timed[k]["avg_ms"] * timed[k]["launches"])
@@ -307,7 +314,7 @@ def main():
                             "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                             "traffic": measured_traffic(dom, n),
                             "alg_bytes": timed[dom]["alg_bytes"]}
-        ab = alg_bytes(n, res["np"])
+        ab = alg_bytes(n, res["np"], args.steps)
         per_step = ("fill_zero", "r2c_z", "fft_y", "fft_x_green", "fft_y_inv", "c2r_z",
                     "qpot", "gather_kick_drift")
         step_bytes = sum(ab[k] for k in per_step)
@@ -334,7 +341,7 @@ def main():
             "finite": re_["finite"],
         }
         if "kernels" in re_:
-            line["evolved"]["kernels"] = kernel_table(re_["kernels"], n, re_["np"])
+            line["evolved"]["kernels"] = kernel_table(re_["kernels"], n, re_["np"], args.steps)
     if trace is not None:
         line["serving"] = serve_section(trace, ics)
         del ics

@@ -334,24 +334,34 @@ pm_status run_poisson(pm_ctx* c, int src, const void* in) {
   return timed(c, kcC2R, [&] { return launch_c2r_z(c->logn, c->spec, c->tw, c->phi, c->stream); });
 }
 
-pm_status run_qpot(pm_ctx* c, const float* delta, bool use_mass, bool energy) {
+pm_status run_qpot(pm_ctx* c, const float* delta, bool use_mass, int out,
+                   const Kick* psi = nullptr) {
   QConst qc = c->qc;
   if (!use_mass) qc.fp64_below = -1.0;
+  if (psi) {
+    qc.psi_g = (float)psi->g;
+    qc.psi_q = (float)psi->q;
+  }
   return timed(c, kcQpot, [&] {
-    return launch_qpot(c->logn, c->fixed, energy, delta, static_cast<const long long*>(c->mass),
+    return launch_qpot(c->logn, c->fixed, out, delta, static_cast<const long long*>(c->mass),
                        c->phi, c->q, qc, c->partials, c->stream);
   });
 }
 
 // deposit + Poisson + Q at the given positions, all into the workspace
-// (deposit = false: the mass mesh already holds them, from the fused push)
-pm_status run_fields(pm_ctx* c, const void* pos, bool energy, bool deposit = true) {
+// (deposit = false: the mass mesh already holds them, from the fused push).
+// With psi (and a quantum potential), q receives the kick potential
+// psi->g * phi + psi->q * Q for one gather instead of Q; phi stays phi.
+pm_status run_fields(pm_ctx* c, const void* pos, bool energy, bool deposit = true,
+                     const Kick* psi = nullptr) {
   if (deposit) PM_TRY(run_deposit(c, pos));
   PM_TRY(run_poisson(c, c->fixed ? kSrcMass64 : kSrcAcc32, c->mass));
   c->have_delta = true;
   c->have_phi = true;
-  if (c->has_q || energy) PM_TRY(run_qpot(c, c->delta, true, energy));
-  c->have_q = c->has_q;
+  const bool to_psi = psi && c->has_q && !energy;
+  if (c->has_q || energy)
+    PM_TRY(run_qpot(c, c->delta, true, energy ? kOutEnergy : to_psi ? kOutPsi : kOutQ, psi));
+  c->have_q = c->has_q && !to_psi;
   return PM_OK;
 }
 
@@ -513,10 +523,10 @@ pm_status pm_poisson(pm_ctx* c, const float* d_delta, float* d_phi) {
 pm_status pm_qpot(pm_ctx* c, const float* d_delta, float* d_q) {
   if (!c) return PM_EINVAL;
   if (d_delta) {
-    PM_TRY(run_qpot(c, d_delta, false, false));
+    PM_TRY(run_qpot(c, d_delta, false, kOutQ));
   } else {
     if (!c->have_delta) return PM_ESTATE;
-    PM_TRY(run_qpot(c, c->delta, c->fixed, false));
+    PM_TRY(run_qpot(c, c->delta, c->fixed, kOutQ));
   }
   c->have_q = true;
   c->fields_at_pos = false;
@@ -655,13 +665,24 @@ pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int
     std::swap(cur_vel, alt_vel);
     return PM_OK;
   };
+  // the kick before drift s: closing half of step s - 1 plus opening half of step s
+  auto merged = [&](int s, const Kick& close) {
+    const Kick open = kick(c->p, times[s], midpoint(c->p, times[s], times[s + 1]));
+    return Kick{close.g + open.g, close.q + open.q};
+  };
+  // Inside the call the fields for the next gather are written as the one
+  // potential psi = F_g phi + F_q Q it needs; the fields left at the end of
+  // the call stay phi and Q, for the closing half-kick and a continued call.
+  bool psi = false;
   if (!((flags & PM_CONTINUE) && c->fields_at_pos)) {
     // Sorting before the opening deposit lets it run from tiles: from a
     // clustered state the direct deposit contends on shared cells (6.5 ms
     // against well under 1 ms at 256^3, a = 0.5).  The integer deposit does
     // not depend on the order.
     if (c->fixed && !c->sorted && (sort_auto || sort_every > 0)) PM_TRY(sort_step());
-    PM_TRY(run_fields(c, cur_pos, false));
+    const Kick k0 = merged(0, Kick{0.0, 0.0});
+    PM_TRY(run_fields(c, cur_pos, false, true, &k0));
+    psi = c->has_q;
   }
   c->fields_at_pos = false;
   const double fdu = c->fixed ? ldexp(1.0, c->B) : 1.0;
@@ -669,7 +690,7 @@ pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int
   for (int s = 0; s < nsteps; ++s) {
     const double t0 = times[s], t1 = times[s + 1];
     const double tm = midpoint(c->p, t0, t1);
-    const Kick open = kick(c->p, t0, tm);
+    const Kick kk = merged(s, close);
     if (sort_auto) {
       poll_sort_stat(c);
       if (!c->sorted || c->since_sort >= c->sort_interval) PM_TRY(sort_step());
@@ -677,19 +698,33 @@ pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int
       PM_TRY(sort_step());
     }
     GatherConst gc;
-    gc.fg = (float)(close.g + open.g);
-    gc.fq = (float)(close.q + open.q);
+    if (psi) {
+      gc.fg = 1.0f;
+      gc.fq = 0.0f;
+      gc.psi = 1;
+    } else {
+      gc.fg = (float)kk.g;
+      gc.fq = (float)kk.q;
+    }
     gc.fd_units = drift(c->p, t0, t1) * fdu;
     // gather + kick + drift, fused with the deposit of the drifted particles
     PM_TRY(timed(c, kcFill, [&] { return launch_fill_zero(c->mass, 8 * c->ncell + kStrayBytes, c->stream); }));
     PM_TRY(timed(c, kcGatherKD, [&] {
-      return launch_gather(c->fixed, c->has_q, true, c->logn, cur_pos, cur_vel, c->phi, c->q,
-                           c->np, gc, c->sorted ? &c->tmap : nullptr, c->mass, c->stream);
+      return launch_gather(c->fixed, c->has_q && !psi, true, c->logn, cur_pos, cur_vel,
+                           psi ? c->q : c->phi, c->q, c->np, gc,
+                           c->sorted ? &c->tmap : nullptr, c->mass, c->stream);
     }));
     ++c->since_sort;
     if (sort_auto && !c->stat_pending) PM_TRY(sample_sort_stat(c));
-    PM_TRY(run_fields(c, cur_pos, false, false));
     close = kick(c->p, tm, t1);
+    if (s + 1 < nsteps) {
+      const Kick kn = merged(s + 1, close);
+      PM_TRY(run_fields(c, cur_pos, false, false, &kn));
+      psi = c->has_q;
+    } else {
+      PM_TRY(run_fields(c, cur_pos, false, false));
+      psi = false;
+    }
   }
   GatherConst gc;
   gc.fg = (float)close.g;
@@ -926,14 +961,15 @@ pm_status pm_batch_step(pm_batch* b, void* d_pos, float* d_vel, int32_t nactive,
   };
   bool sorted = all_sorted;
   const float gscale = (float)(-c->S * 2.0 / ((double)c->N * c->N * c->N));
-  auto fields = [&](const Batch& bq) -> pm_status {
+  // to_psi: q receives psi = F_g phi + F_q Q with the factors of bq's row
+  auto fields = [&](const Batch& bq, bool to_psi) -> pm_status {
     PM_TRY(dev(launch_r2c_z(c->logn, c->fixed ? kSrcMass64 : kSrcAcc32, c->mass, c->delta,
                             c->spec, c->tw, c->conv, c->stream, bt)));
     PM_TRY(dev(launch_fft_y(c->logn, c->spec, c->tw, false, c->stream, bt)));
     PM_TRY(dev(launch_fft_x_green(c->logn, c->spec, c->tw, c->s2, gscale, c->stream, bt)));
     PM_TRY(dev(launch_fft_y(c->logn, c->spec, c->tw, true, c->stream, bt)));
     PM_TRY(dev(launch_c2r_z(c->logn, c->spec, c->tw, c->phi, c->stream, bt)));
-    return dev(launch_qpot(c->logn, c->fixed, false, c->delta,
+    return dev(launch_qpot(c->logn, c->fixed, to_psi ? kOutPsi : kOutQ, c->delta,
                            static_cast<const long long*>(c->mass), c->phi, c->q, c->qc,
                            c->partials, c->stream, bq));
   };
@@ -969,18 +1005,28 @@ pm_status pm_batch_step(pm_batch* b, void* d_pos, float* d_vel, int32_t nactive,
                                                    static_cast<float*>(c->mass), c->stream, bt)
                         : launch_deposit_f32(static_cast<const float*>(d_pos), c->np, c->logn,
                                              static_cast<float*>(c->mass), c->stream, bt)));
-    PM_TRY(fields(row(0)));
+    PM_TRY(fields(row(0), true));
   }
+  // inside the call the fields hold psi for the next row's factors; the last
+  // fields stay phi and Q (closing half-kick, continued calls)
+  bool psi = !(flags & PM_CONTINUE);
   for (int i = 0; i < nactive; ++i) b->fields_ok[slots[i]] = 0;
   GatherConst unused;
   unused.fg = unused.fq = 0.0f;
   unused.fd_units = 0.0;
+  GatherConst gpsi;
+  gpsi.fg = 1.0f;
+  gpsi.fq = 0.0f;
+  gpsi.fd_units = 0.0;
+  gpsi.psi = 1;
   for (int k = 0; k < nsteps; ++k) {
     if (sort_every > 0 && k % sort_every == 0) PM_TRY(sort_all());
     PM_TRY(dev(launch_fill_zero(c->mass, 8 * c->ncell + kStrayBytes, c->stream, bt)));
-    PM_TRY(dev(launch_gather(c->fixed, true, true, c->logn, d_pos, d_vel, c->phi, c->q, c->np,
-                             unused, sorted ? &c->tmap : nullptr, c->mass, c->stream, row(k))));
-    PM_TRY(fields(row(k)));
+    PM_TRY(dev(launch_gather(c->fixed, !psi, true, c->logn, d_pos, d_vel, psi ? c->q : c->phi,
+                             c->q, c->np, psi ? gpsi : unused, sorted ? &c->tmap : nullptr,
+                             c->mass, c->stream, row(k))));
+    psi = k + 1 < nsteps;
+    PM_TRY(fields(row(psi ? k + 1 : k), psi));
   }
   PM_TRY(dev(launch_gather(c->fixed, true, false, c->logn, d_pos, d_vel, c->phi, c->q, c->np,
                            unused, sorted ? &c->tmap : nullptr, nullptr, c->stream, row(nsteps))));

@@ -139,9 +139,9 @@ __device__ __forceinline__ void push(void* __restrict__ pos, float* __restrict__
 template <int LOGN, bool HAS_Q>
 __device__ __forceinline__ float mesh_f(const float* __restrict__ phi, const float* __restrict__ q,
                                         const GatherConst& gc, size_t idx) {
-  float v = gc.fg * phi[idx];
-  if constexpr (HAS_Q) v += gc.fq * q[idx];
-  return v;
+  // the same rounding as the stencil's psi output: fq * Q added by one fma
+  if constexpr (HAS_Q) return fmaf(gc.fq, q[idx], gc.fg * phi[idx]);
+  return gc.fg * phi[idx];
 }
 
 // Weights of the drifted particle for the fused deposit.
@@ -171,8 +171,10 @@ __global__ void __launch_bounds__(kBlock) k_gather(void* __restrict__ pos,
     mass_v = woff(mass_v, bt, sl);
     if (bt.consts) {
       const SlotConst& sc = bt.consts[blockIdx.y];
-      gc.fg = sc.fg;
-      gc.fq = sc.fq;
+      if (!gc.psi) {
+        gc.fg = sc.fg;
+        gc.fq = sc.fq;
+      }
       gc.fd_units = sc.fd_units;
     }
   }
@@ -228,8 +230,10 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather_tiled(void* __restrict_
     tm.chunk_start = woff(tm.chunk_start, bt, sl);
     if (bt.consts) {
       const SlotConst& sc = bt.consts[blockIdx.y];
-      gc.fg = sc.fg;
-      gc.fq = sc.fq;
+      if (!gc.psi) {
+        gc.fg = sc.fg;
+        gc.fq = sc.fq;
+      }
       gc.fd_units = sc.fd_units;
     }
   }

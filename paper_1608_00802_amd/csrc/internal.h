@@ -173,12 +173,19 @@ struct QConst {
   double fp64_below;      // FP64 path threshold (fixed form; <= 0 disables)
   long long mbar;         // mean integer mass per cell
   double inv_mbar;        // 1 / mbar
+  float psi_g, psi_q;     // kOutPsi: factors on phi and Q (a batch takes them per slot)
 };
+// What the Q stencil writes: Q; Q and the FP64 energy partials; or the
+// combined kick potential psi = psi_g * phi + psi_q * Q that the next gather
+// differentiates (one mesh read per cell there instead of two).
+enum QOut : int { kOutQ = 0, kOutEnergy = 1, kOutPsi = 2 };
 
 struct GatherConst {
   float fg;           // factor on -grad(phi)
   float fq;           // factor on -grad(Q)
   double fd_units;    // drift factor times 2^(32 - log2 N) (fixed) or drift factor (float)
+  int psi = 0;        // phi holds psi with its factors applied: fg = 1, fq unused, and a
+                      // batch's per-slot kick factors are not applied again
 };
 
 // ---- deposit.hip
@@ -268,7 +275,7 @@ hipError_t launch_c2r_z(int logn, const float2* spec, const float2* tw, float* o
                         hipStream_t s, const Batch& bt = Batch());
 
 // ---- stencil.hip
-hipError_t launch_qpot(int logn, bool fixed, bool energy, const float* delta,
+hipError_t launch_qpot(int logn, bool fixed, int out, const float* delta,
                        const long long* mass, const float* phi, float* q,
                        const QConst& qc, double* partials, hipStream_t s,
                        const Batch& bt = Batch());

@@ -9,10 +9,11 @@
 // exact integer mass (the 1/sqrt(rho) division is ill-conditioned there).
 // Plain FP32 form: sqrt(R) and the stencil directly in FP32.
 //
-// With ENERGY, each block also writes FP64 partial sums of delta*phi (for the
-// potential energy) and of sum_d (sqrt R_{j+e_d} - sqrt R_j)^2 (gradient energy
-// K_rho of Eq. (6), forward differences); a single-block kernel reduces the
-// partials in a fixed order, so the totals are deterministic.
+// With kOutEnergy, each block also writes FP64 partial sums of delta*phi (for
+// the potential energy) and of sum_d (sqrt R_{j+e_d} - sqrt R_j)^2 (gradient
+// energy K_rho of Eq. (6), forward differences); a single-block kernel reduces
+// the partials in a fixed order, so the totals are deterministic.  With
+// kOutPsi the output is psi_g * phi + psi_q * Q instead of Q.
 #include "internal.h"
 
 namespace fdm {
@@ -30,7 +31,7 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return t;
 }
 
-template <int LOGN, bool FIXED, bool ENERGY>
+template <int LOGN, bool FIXED, int OUT>
 __global__ void __launch_bounds__(kBlock) k_qpot(const float* __restrict__ delta,
                                                  const long long* __restrict__ mass,
                                                  const float* __restrict__ phi,
@@ -46,6 +47,8 @@ __global__ void __launch_bounds__(kBlock) k_qpot(const float* __restrict__ delta
     if (bt.consts) {
       qc.coef = bt.consts[blockIdx.y].qcoef;
       qc.coef_d = bt.consts[blockIdx.y].qcoef_d;
+      qc.psi_g = bt.consts[blockIdx.y].fg;
+      qc.psi_q = bt.consts[blockIdx.y].fq;
     }
   }
   constexpr int N = 1 << LOGN;
@@ -95,8 +98,11 @@ __global__ void __launch_bounds__(kBlock) k_qpot(const float* __restrict__ delta
     const float lap = ((sn[0] + sn[1]) + (sn[2] + sn[3]) + (sn[4] + sn[5])) - 6.0f * sc;
     qv = qc.coef * lap / sc;
   }
-  q[i] = qv;
-  if constexpr (ENERGY) {
+  if constexpr (OUT == kOutPsi)
+    q[i] = fmaf(qc.psi_q, qv, qc.psi_g * phi[i]);
+  else
+    q[i] = qv;
+  if constexpr (OUT == kOutEnergy) {
     __shared__ double red[kBlock / 64];
     const double w = (double)dc * (double)phi[i];
     const double e0 = (double)(sn[0] - sc), e1 = (double)(sn[2] - sc), e2 = (double)(sn[4] - sc);
@@ -125,7 +131,7 @@ __device__ __forceinline__ float s_of(float d, const QConst& qc) {
   return sqrtf(r >= qc.floor_f ? r : qc.floor_f);
 }
 
-template <int LOGN, bool FIXED, bool ENERGY>
+template <int LOGN, bool FIXED, int OUT>
 __global__ void __launch_bounds__(kBlock) k_qpot_tiled(const float* __restrict__ delta,
                                                        const long long* __restrict__ mass,
                                                        const float* __restrict__ phi,
@@ -141,6 +147,8 @@ __global__ void __launch_bounds__(kBlock) k_qpot_tiled(const float* __restrict__
     if (bt.consts) {
       qc.coef = bt.consts[blockIdx.y].qcoef;
       qc.coef_d = bt.consts[blockIdx.y].qcoef_d;
+      qc.psi_g = bt.consts[blockIdx.y].fg;
+      qc.psi_q = bt.consts[blockIdx.y].fq;
     }
   }
   constexpr int N = 1 << LOGN;
@@ -270,8 +278,11 @@ __global__ void __launch_bounds__(kBlock) k_qpot_tiled(const float* __restrict__
     } else {
       qv = qc.coef * lap / s_cur;
     }
-    q[i] = qv;
-    if constexpr (ENERGY) {
+    if constexpr (OUT == kOutPsi)
+      q[i] = fmaf(qc.psi_q, qv, qc.psi_g * phi[i]);
+    else
+      q[i] = qv;
+    if constexpr (OUT == kOutEnergy) {
       wsum += (double)delta[i] * (double)phi[i];
       const double e0 = (double)(s_next - s_cur), e1 = (double)(sy_cur - s_cur),
                    e2 = (double)(sz_cur - s_cur);
@@ -285,7 +296,7 @@ __global__ void __launch_bounds__(kBlock) k_qpot_tiled(const float* __restrict__
     d_prev = d_c;
     near_cur = near_next;
   }
-  if constexpr (ENERGY) {
+  if constexpr (OUT == kOutEnergy) {
     __shared__ double red[kBlock / 64];
     const double ws = block_sum(wsum, red);
     const double us = block_sum(usum, red);
@@ -303,26 +314,31 @@ int qpot_blocks(int logn) {
   return (int)(((size_t)1 << (3 * logn)) / kBlock);
 }
 
-hipError_t launch_qpot(int logn, bool fixed, bool energy, const float* delta,
+hipError_t launch_qpot(int logn, bool fixed, int out, const float* delta,
                        const long long* mass, const float* phi, float* q, const QConst& qc,
                        double* partials, hipStream_t s, const Batch& bt) {
   const dim3 g((unsigned)qpot_blocks(logn), bt.count);
+  if (out != kOutQ && out != kOutEnergy && out != kOutPsi) return hipErrorInvalidValue;
+#define K_(KERNEL, LN, FX)                                                                   \
+  {                                                                                          \
+    if (out == kOutEnergy)                                                                   \
+      hipLaunchKernelGGL((KERNEL<LN, FX, kOutEnergy>), g, dim3(kBlock), 0, s, delta, mass,    \
+                         phi, q, qc, partials, bt);                                          \
+    else if (out == kOutPsi)                                                                 \
+      hipLaunchKernelGGL((KERNEL<LN, FX, kOutPsi>), g, dim3(kBlock), 0, s, delta, mass, phi,  \
+                         q, qc, partials, bt);                                               \
+    else                                                                                     \
+      hipLaunchKernelGGL((KERNEL<LN, FX, kOutQ>), g, dim3(kBlock), 0, s, delta, mass, phi, q, \
+                         qc, partials, bt);                                                  \
+  }
 #ifndef FDM_QPOT_SIMPLE
   if (logn >= 5) {
-#define T_(LN)                                                                               \
-  {                                                                                          \
-    if (fixed && energy)                                                                     \
-      hipLaunchKernelGGL((k_qpot_tiled<LN, true, true>), g, dim3(kBlock), 0, s, delta, mass,  \
-                         phi, q, qc, partials, bt);                                              \
-    else if (fixed)                                                                          \
-      hipLaunchKernelGGL((k_qpot_tiled<LN, true, false>), g, dim3(kBlock), 0, s, delta, mass, \
-                         phi, q, qc, partials, bt);                                              \
-    else if (energy)                                                                         \
-      hipLaunchKernelGGL((k_qpot_tiled<LN, false, true>), g, dim3(kBlock), 0, s, delta, mass, \
-                         phi, q, qc, partials, bt);                                              \
-    else                                                                                     \
-      hipLaunchKernelGGL((k_qpot_tiled<LN, false, false>), g, dim3(kBlock), 0, s, delta,     \
-                         mass, phi, q, qc, partials, bt);                                        \
+#define T_(LN)                          \
+  {                                     \
+    if (fixed)                          \
+      K_(k_qpot_tiled, LN, true)        \
+    else                                \
+      K_(k_qpot_tiled, LN, false)       \
   }
     switch (logn) {
       case 5: T_(5); break;
@@ -336,23 +352,16 @@ hipError_t launch_qpot(int logn, bool fixed, bool energy, const float* delta,
     return hipGetLastError();
   }
 #endif
-#define L_(LN)                                                                            \
-  {                                                                                       \
-    if (fixed && energy)                                                                  \
-      hipLaunchKernelGGL((k_qpot<LN, true, true>), g, dim3(kBlock), 0, s, delta, mass, phi, \
-                         q, qc, partials, bt);                                            \
-    else if (fixed)                                                                       \
-      hipLaunchKernelGGL((k_qpot<LN, true, false>), g, dim3(kBlock), 0, s, delta, mass,   \
-                         phi, q, qc, partials, bt);                                           \
-    else if (energy)                                                                      \
-      hipLaunchKernelGGL((k_qpot<LN, false, true>), g, dim3(kBlock), 0, s, delta, mass,   \
-                         phi, q, qc, partials, bt);                                           \
-    else                                                                                  \
-      hipLaunchKernelGGL((k_qpot<LN, false, false>), g, dim3(kBlock), 0, s, delta, mass,  \
-                         phi, q, qc, partials, bt);                                           \
+#define L_(LN)                   \
+  {                              \
+    if (fixed)                   \
+      K_(k_qpot, LN, true)       \
+    else                         \
+      K_(k_qpot, LN, false)      \
   }
   FDM_LOGN_SWITCH(logn, L_)
 #undef L_
+#undef K_
   return hipGetLastError();
 }
 
