@@ -124,10 +124,11 @@ def test_poisson_random_vs_oracle(pm, gpu, n):
 
 # ------------------------------------------------------------------ Q
 
+@pytest.mark.parametrize("n", [64, 128])
 @pytest.mark.parametrize("precision", [1, 0])
-def test_qpot_vs_oracle_smooth(pm, gpu, precision):
+def test_qpot_vs_oracle_smooth(pm, gpu, precision, n):
+    """Q of a Zel'dovich state against the oracle's Q of the same density."""
     import torch
-    n = 64
     st = zeldovich_state(n, 10.0, 0.3, seed=7, m_ev=1e-22)
     lp, op = cosmo_setup(n, 10.0, 1e-22, precision=precision)
     ctx = _ctx(pm, lp, gpu)
@@ -141,10 +142,10 @@ def test_qpot_vs_oracle_smooth(pm, gpu, precision):
     assert err < (1e-5 if precision == 1 else 1e-3), err
 
 
-def test_qpot_near_empty_cells_fp64_path(pm, gpu):
+@pytest.mark.parametrize("n,npart,width", [(32, 20000, 1.5), (128, 200000, 6.0)])
+def test_qpot_near_empty_cells_fp64_path(pm, gpu, n, npart, width):
     import torch
-    n = 32
-    st = _clustered_state(n, 20000, seed=5)
+    st = _clustered_state(n, npart, seed=5, width=width)
     lp, op = cosmo_setup(n, 5.0, 1e-22)
     lp.n_part = st.npart
     ctx = _ctx(pm, lp, gpu)
@@ -269,8 +270,8 @@ def test_single_mode_drift_100_steps(pm, gpu, precision):
 
 # ------------------------------------------------------------------ energies
 
-def test_energy_vs_oracle(pm, gpu):
-    n = 32
+@pytest.mark.parametrize("n", [32, 128])
+def test_energy_vs_oracle(pm, gpu, n):
     st = zeldovich_state(n, 2.0, 0.1, seed=4, m_ev=2.5e-22)
     lp, op = cosmo_setup(n, 2.0, 2.5e-22)
     ctx = _ctx(pm, lp, gpu)
