@@ -16,12 +16,16 @@
 //   5. z-pass  (C2R): pack the Hermitian half-rows into a length-N/2 complex
 //      sequence, inverse FFT, write real rows.
 //
-// Inside a block, each row is transformed by a Stockham autosort FFT with
-// radix-4 stages (one leading radix-2 stage for odd log2 lengths): every
-// thread loads its butterflies' inputs into registers, the block barriers,
-// then results are written back to the same LDS rows -- one LDS buffer, two
-// barriers per stage, natural order at the end.  Twiddles come from an FP64-
-// built table exp(-2 pi i k / N) staged in LDS.
+// The y and x passes split each length-N transform into two factors whose
+// short DFTs run in registers, with one exchange through LDS between them
+// (register FFTs below); the x pass keeps the forward result in registers
+// through the Green's function into the inverse transform.  The z passes
+// transform rows staged in LDS with a Stockham autosort FFT of radix-4 stages
+// (one leading radix-2 stage for odd log2 lengths): every thread loads its
+// butterflies' inputs into registers, the block barriers, then results are
+// written back to the same LDS rows -- one LDS buffer, two barriers per
+// stage, natural order at the end.  Twiddles come from an FP64-built table
+// exp(-2 pi i k / N) staged in LDS.
 #include "internal.h"
 
 namespace fdm {
@@ -125,29 +129,82 @@ __device__ __forceinline__ void fft_rows(float2* __restrict__ buf, const float2*
 #ifndef FDM_FFT_Z_ELEMS
 #define FDM_FFT_Z_ELEMS 4096
 #endif
-#ifndef FDM_FFT_Y_ELEMS
-#define FDM_FFT_Y_ELEMS 2048
-#endif
-#ifndef FDM_FFT_X_ELEMS
-#define FDM_FFT_X_ELEMS 2048
-#endif
-#ifndef FDM_FFT_X_MINCOL
-#define FDM_FFT_X_MINCOL 8
-#endif
-// Rows (complex elements / N) per block of each pass, and at least
-// FDM_FFT_X_MINCOL consecutive y columns (64-byte segments) per x-pass
-// block.  Small tiles leave room for four or more blocks per CU, so one
-// block's transform overlaps another's loads (256^3: 30 us less per step
-// than tiles twice as large).
+// Rows (complex elements / N) per block of the z passes.  Small tiles leave
+// room for four or more blocks per CU, so one block's transform overlaps
+// another's loads (256^3: 30 us less per step than tiles twice as large).
 template <int N>
 struct Tiles {
-  static constexpr int H = N / 2;
-  static constexpr int ZE = FDM_FFT_Z_ELEMS, YE = FDM_FFT_Y_ELEMS, XE = FDM_FFT_X_ELEMS;
-  static constexpr int MC = FDM_FFT_X_MINCOL;
+  static constexpr int ZE = FDM_FFT_Z_ELEMS;
   static constexpr int TZ = (ZE / N < N) ? ZE / N : N;   // rows per z-pass block
-  static constexpr int TY = (YE / N < N) ? YE / N : N;   // rows per y-pass block
-  static constexpr int TC = (XE / N >= MC) ? ((XE / N < N) ? XE / N : N) : MC;  // x-pass columns
 };
+
+// ---------------------------------------------------------------- register FFTs
+// An L-point transform split as L = F1 x F2: F2 DFTs of length F1 over
+// n = F2 n1 + n2, the twiddles W_L^{n2 k1}, then F1 DFTs of length F2 over
+// n2, giving X[k1 + F1 k2].  Each short DFT runs in one thread's registers,
+// so a transform makes one trip through LDS (the exchange between the two
+// factors) instead of one per radix-4 stage.  The y and x passes use this
+// form; the z passes (with their real-data packing) use fft_rows.
+constexpr int kRegBlock = 128;   // threads per block of the register-FFT passes
+
+template <int L>
+struct Split {
+  static constexpr int LG = ilog2c(L);
+  static constexpr int R1 = 1 << ((LG + 1) / 2);   // first factor (the larger)
+  static constexpr int R2 = L / R1;
+};
+
+constexpr int bitrev_c(int i, int bits) {
+  int r = 0;
+  for (int b = 0; b < bits; ++b) r |= ((i >> b) & 1) << (bits - 1 - b);
+  return r;
+}
+
+// In-register radix-2 DFT of length R (natural order in and out);
+// tw[m * TS] = exp(-2 pi i m / R).  INV: exp(+i), no scaling.
+template <int R, bool INV, int TS>
+__device__ __forceinline__ void dft_reg(float2 (&v)[R], const float2* __restrict__ tw) {
+  constexpr int B = ilog2c(R);
+  float2 a[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) a[i] = v[bitrev_c(i, B)];
+#pragma unroll
+  for (int len = 2; len <= R; len <<= 1) {
+#pragma unroll
+    for (int i = 0; i < R; i += len) {
+#pragma unroll
+      for (int j = 0; j < len / 2; ++j) {
+        float2 t = a[i + j + len / 2];
+        const int m = j * (R / len);               // twiddle W_R^m
+        if (m != 0) {
+          if (4 * m == R) {
+            t = INV ? make_float2(-t.y, t.x) : make_float2(t.y, -t.x);   // times +i / -i
+          } else {
+            const float2 w = tw[m * TS];
+            t = INV ? cmulc(t, w) : cmul(t, w);
+          }
+        }
+        a[i + j + len / 2] = csub(a[i + j], t);
+        a[i + j] = cadd(a[i + j], t);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i) v[i] = a[i];
+}
+
+// First factor of an L-point transform for one n2: v[n1] = x[F2 n1 + n2] in,
+// v[k1] = W_L^{n2 k1} * sum_n1 x[F2 n1 + n2] W_F1^{n1 k1} out.
+// tw[m * TWS] = exp(-2 pi i m / L).
+template <int L, int F1, bool INV, int TWS = 1>
+__device__ __forceinline__ void fft_first(float2 (&v)[F1], int n2, const float2* __restrict__ tw) {
+  dft_reg<F1, INV, (L / F1) * TWS>(v, tw);
+#pragma unroll
+  for (int k1 = 1; k1 < F1; ++k1) {
+    const float2 w = tw[((n2 * k1) & (L - 1)) * TWS];
+    v[k1] = INV ? cmulc(v[k1], w) : cmul(v[k1], w);
+  }
+}
 
 // ---------------------------------------------------------------- pass 1
 template <int LOGN, int SRC>
@@ -213,70 +270,171 @@ __global__ void __launch_bounds__(kBlock) k_r2c_z(const void* __restrict__ in,
   }
 }
 
-// ---------------------------------------------------------------- passes 2, 4
+// ---------------------------------------------------------------- passes 2-4
+// Register-FFT versions of passes 2-4 (kRegBlock threads).  The y pass
+// reads each row's F1-strided elements straight into registers and writes
+// the result from registers; the x pass keeps the forward transform's output
+// in registers for the Green's function and the inverse transform's first
+// factor (whose inputs, X[k1 + R1 k2] for one k1, are exactly what one
+// thread holds), so each transform crosses LDS once.
+template <int N>
+struct RegTiles {
+  static constexpr int R1 = Split<N>::R1, R2 = Split<N>::R2;
+  static constexpr int RMAX = R1 > R2 ? R1 : R2;
+  static constexpr int RY0 = kRegBlock / R2;                       // y-pass rows per block
+  static constexpr int RY = RY0 < N ? RY0 : N;
+  static constexpr int TC0 = (kRegBlock / RMAX > 8) ? kRegBlock / RMAX : 8;
+  static constexpr int TC = TC0 < N ? TC0 : N;                     // x-pass columns per block
+};
+
 template <int LOGN, bool INV>
-__global__ void __launch_bounds__(kBlock) k_fft_y(float2* __restrict__ spec,
-                                                  const float2* __restrict__ tw, Batch bt) {
+__global__ void __launch_bounds__(kRegBlock) k_fft_y_reg(float2* __restrict__ spec,
+                                                         const float2* __restrict__ tw,
+                                                         Batch bt) {
   spec = woff(spec, bt, bslot(bt));
   constexpr int N = 1 << LOGN;
-  constexpr int TY = Tiles<N>::TY;
-  constexpr int LP = N + 1;
-  __shared__ float2 buf[TY * LP];
+  constexpr int R1 = Split<N>::R1, R2 = Split<N>::R2;
+  constexpr int RY = RegTiles<N>::RY;
+  constexpr int XP = R1 + 1;                  // exchange: ex[r][n2][k1], k1 padded
+  constexpr int NA = RY * R2, NB = RY * R1;   // work items of the two factors
+  constexpr int PA = (NA + kRegBlock - 1) / kRegBlock, PB = (NB + kRegBlock - 1) / kRegBlock;
+  __shared__ float2 ex[RY * R2 * XP];
   __shared__ float2 tws[N];
   const int tid = threadIdx.x;
-  const size_t row0 = (size_t)blockIdx.x * TY;
-  for (int k = tid; k < N; k += kBlock) tws[k] = tw[k];
-  for (int idx = tid; idx < TY * N; idx += kBlock) {
-    const int r = idx / N, n = idx % N;
-    buf[r * LP + n] = spec[(row0 + r) * N + n];
+  const size_t row0 = (size_t)blockIdx.x * RY;
+  float2 v[PA][R1];
+#pragma unroll
+  for (int p = 0; p < PA; ++p) {
+    const int it = tid + p * kRegBlock;
+    if (NA % kRegBlock == 0 || it < NA) {
+      const int r = it / R2, n2 = it % R2;
+#pragma unroll
+      for (int n1 = 0; n1 < R1; ++n1) v[p][n1] = spec[(row0 + r) * N + R2 * n1 + n2];
+    }
+  }
+  for (int k = tid; k < N; k += kRegBlock) tws[k] = tw[k];
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < PA; ++p) {
+    const int it = tid + p * kRegBlock;
+    if (NA % kRegBlock == 0 || it < NA) {
+      const int r = it / R2, n2 = it % R2;
+      fft_first<N, R1, INV>(v[p], n2, tws);
+#pragma unroll
+      for (int k1 = 0; k1 < R1; ++k1) ex[(r * R2 + n2) * XP + k1] = v[p][k1];
+    }
   }
   __syncthreads();
-  fft_rows<N, TY, kBlock, 1, INV>(buf, tws);
-  for (int idx = tid; idx < TY * N; idx += kBlock) {
-    const int r = idx / N, n = idx % N;
-    spec[(row0 + r) * N + n] = buf[r * LP + n];
+#pragma unroll
+  for (int p = 0; p < PB; ++p) {
+    const int it = tid + p * kRegBlock;
+    if (NB % kRegBlock == 0 || it < NB) {
+      const int r = it / R1, k1 = it % R1;
+      float2 u[R2];
+#pragma unroll
+      for (int n2 = 0; n2 < R2; ++n2) u[n2] = ex[(r * R2 + n2) * XP + k1];
+      dft_reg<R2, INV, N / R2>(u, tws);
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) spec[(row0 + r) * N + k1 + R1 * k2] = u[k2];
+    }
   }
 }
 
-// ---------------------------------------------------------------- pass 3
 template <int LOGN>
-__global__ void __launch_bounds__(kBlock) k_fft_x_green(float2* __restrict__ spec,
-                                                        const float2* __restrict__ tw,
-                                                        const float* __restrict__ s2,
-                                                        float green_scale, Batch bt) {
+__global__ void __launch_bounds__(kRegBlock) k_fft_x_green_reg(float2* __restrict__ spec,
+                                                               const float2* __restrict__ tw,
+                                                               const float* __restrict__ s2,
+                                                               float green_scale, Batch bt) {
   spec = woff(spec, bt, bslot(bt));
   constexpr int N = 1 << LOGN;
-  constexpr int TC = Tiles<N>::TC;
-  constexpr int LP = N + 1;
-  __shared__ float2 buf[TC * LP];
+  constexpr int R1 = Split<N>::R1, R2 = Split<N>::R2;
+  constexpr int TC = RegTiles<N>::TC;
+  // forward exchange ex[c][n2][k1] (k1 < R1, padded), inverse ex[c][k1][k1']
+  // (k1' < R2, padded); one buffer, the larger of the two
+  constexpr int XF = R2 * (R1 + 1), XI = R1 * (R2 + 1);
+  constexpr int XS = XF > XI ? XF : XI;
+  constexpr int NA = TC * R2, NB = TC * R1;   // items: first factor (R1 values) / second (R2 values)
+  constexpr int PA = (NA + kRegBlock - 1) / kRegBlock, PB = (NB + kRegBlock - 1) / kRegBlock;
+  __shared__ float2 ex[TC * XS];
   __shared__ float2 tws[N];
   __shared__ float s2s[N];
   const int tid = threadIdx.x;
   const int b = (int)xcd_block(blockIdx.x, gridDim.x, xcd_group(FDM_XCD_FFTX, gridDim.x));
   const int kz = b / (N / TC);
   const int y0 = (b % (N / TC)) * TC;
-  for (int k = tid; k < N; k += kBlock) {
+  auto at = [&](int x, int c) -> float2& { return spec[((size_t)kz * N + x) * N + y0 + c]; };
+  // items of the first factor: c fastest, so a wave reads TC consecutive y
+  float2 v[PA][R1];
+#pragma unroll
+  for (int p = 0; p < PA; ++p) {
+    const int it = tid + p * kRegBlock;
+    if (NA % kRegBlock == 0 || it < NA) {
+      const int c = it % TC, n2 = it / TC;
+#pragma unroll
+      for (int n1 = 0; n1 < R1; ++n1) v[p][n1] = at(R2 * n1 + n2, c);
+    }
+  }
+  for (int k = tid; k < N; k += kRegBlock) {
     tws[k] = tw[k];
     s2s[k] = s2[k];
   }
-  for (int idx = tid; idx < N * TC; idx += kBlock) {
-    const int xk = idx / TC, c = idx % TC;
-    buf[c * LP + xk] = spec[((size_t)kz * N + xk) * N + y0 + c];
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < PA; ++p) {
+    const int it = tid + p * kRegBlock;
+    if (NA % kRegBlock == 0 || it < NA) {
+      const int c = it % TC, n2 = it / TC;
+      fft_first<N, R1, false>(v[p], n2, tws);
+#pragma unroll
+      for (int k1 = 0; k1 < R1; ++k1) ex[c * XS + n2 * (R1 + 1) + k1] = v[p][k1];
+    }
   }
   __syncthreads();
-  fft_rows<N, TC, kBlock, 1, false>(buf, tws);
+  // second factor: item (c, k1) gets X[k1 + R1 k2], k2 < R2; times G; then
+  // the inverse transform's first factor over the same values (n = R1 k2 + k1)
+  float2 u[PB][R2];
   const float s2z = s2s[kz];
-  for (int idx = tid; idx < TC * N; idx += kBlock) {
-    const int c = idx / N, kx = idx % N;
-    const float k2 = s2s[kx] + s2s[y0 + c] + s2z;
-    const float g = (k2 > 0.0f) ? green_scale / k2 : 0.0f;
-    buf[c * LP + kx] = cscale(buf[c * LP + kx], g);
+#pragma unroll
+  for (int p = 0; p < PB; ++p) {
+    const int it = tid + p * kRegBlock;
+    if (NB % kRegBlock == 0 || it < NB) {
+      const int c = it % TC, k1 = it / TC;
+#pragma unroll
+      for (int n2 = 0; n2 < R2; ++n2) u[p][n2] = ex[c * XS + n2 * (R1 + 1) + k1];
+      dft_reg<R2, false, N / R2>(u[p], tws);
+      const float s2yz = s2s[y0 + c] + s2z;
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) {
+        const float k2sum = s2s[k1 + R1 * k2] + s2yz;
+        const float g = (k2sum > 0.0f) ? green_scale / k2sum : 0.0f;
+        u[p][k2] = cscale(u[p][k2], g);
+      }
+      fft_first<N, R2, true>(u[p], k1, tws);
+    }
+  }
+  __syncthreads();   // every read of the forward exchange is done
+#pragma unroll
+  for (int p = 0; p < PB; ++p) {
+    const int it = tid + p * kRegBlock;
+    if (NB % kRegBlock == 0 || it < NB) {
+      const int c = it % TC, k1 = it / TC;
+#pragma unroll
+      for (int j = 0; j < R2; ++j) ex[c * XS + k1 * (R2 + 1) + j] = u[p][j];
+    }
   }
   __syncthreads();
-  fft_rows<N, TC, kBlock, 1, true>(buf, tws);
-  for (int idx = tid; idx < N * TC; idx += kBlock) {
-    const int xk = idx / TC, c = idx % TC;
-    spec[((size_t)kz * N + xk) * N + y0 + c] = buf[c * LP + xk];
+  // inverse second factor: item (c, j), j < R2, over k1 < R1: x[j + R2 m]
+#pragma unroll
+  for (int p = 0; p < PA; ++p) {
+    const int it = tid + p * kRegBlock;
+    if (NA % kRegBlock == 0 || it < NA) {
+      const int c = it % TC, j = it / TC;
+#pragma unroll
+      for (int k1 = 0; k1 < R1; ++k1) v[p][k1] = ex[c * XS + k1 * (R2 + 1) + j];
+      dft_reg<R1, true, N / R1>(v[p], tws);
+#pragma unroll
+      for (int m = 0; m < R1; ++m) at(j + R2 * m, c) = v[p][m];
+    }
   }
 }
 
@@ -351,11 +509,11 @@ hipError_t launch_fft_y(int logn, float2* spec, const float2* tw, bool inverse,
 #define L_(LN)                                                                    \
   {                                                                               \
     constexpr int N_ = 1 << LN;                                                   \
-    dim3 g((N_ / 2 + 1) * (N_ / Tiles<N_>::TY), bt.count);                       \
+    dim3 g((N_ / 2 + 1) * (N_ / RegTiles<N_>::RY), bt.count);                     \
     if (inverse)                                                                  \
-      hipLaunchKernelGGL((k_fft_y<LN, true>), g, dim3(kBlock), 0, s, spec, tw, bt); \
+      hipLaunchKernelGGL((k_fft_y_reg<LN, true>), g, dim3(kRegBlock), 0, s, spec, tw, bt); \
     else                                                                          \
-      hipLaunchKernelGGL((k_fft_y<LN, false>), g, dim3(kBlock), 0, s, spec, tw, bt); \
+      hipLaunchKernelGGL((k_fft_y_reg<LN, false>), g, dim3(kRegBlock), 0, s, spec, tw, bt); \
   }
   FDM_LOGN_SWITCH(logn, L_)
 #undef L_
@@ -367,8 +525,8 @@ hipError_t launch_fft_x_green(int logn, float2* spec, const float2* tw, const fl
 #define L_(LN)                                                                      \
   {                                                                                 \
     constexpr int N_ = 1 << LN;                                                     \
-    dim3 g((N_ / 2 + 1) * (N_ / Tiles<N_>::TC), bt.count);                          \
-    hipLaunchKernelGGL((k_fft_x_green<LN>), g, dim3(kBlock), 0, s, spec, tw, s2,    \
+    dim3 g((N_ / 2 + 1) * (N_ / RegTiles<N_>::TC), bt.count);                       \
+    hipLaunchKernelGGL((k_fft_x_green_reg<LN>), g, dim3(kRegBlock), 0, s, spec, tw, s2,  \
                        green_scale, bt);                                            \
   }
   FDM_LOGN_SWITCH(logn, L_)
