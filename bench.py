@@ -161,17 +161,28 @@ TRAFFIC_KERNEL = {"gather_kick_drift": "k_gather_tiled<8, true, false, 1, true>"
                   "c2r_z": "k_c2r_z<8>"}
 
 
+# the sources each kernel family is built from (its counters go stale when one changes)
+TRAFFIC_SOURCES = {"gather_kick_drift": ("gather.hip", "cic.h", "internal.h"),
+                   "deposit": ("deposit.hip", "cic.h", "internal.h"),
+                   "qpot": ("stencil.hip", "internal.h")}
+for _k in ("r2c_z", "fft_y", "fft_x_green", "fft_y_inv", "c2r_z"):
+    TRAFFIC_SOURCES[_k] = ("fft.hip", "internal.h")
+
+
 def measured_traffic(kernel: str, n: int):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None if there is none for this kernel and size or if any kernel source
-    changed since the counters were taken."""
+    None if there is none for this kernel and size or if a source the kernel
+    is built from changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"pm_step_{n}_traffic.json")
     if not os.path.exists(path) or kernel not in TRAFFIC_KERNEL:
         return None
     with open(path) as fh:
         rec = json.load(fh)
+    deps = TRAFFIC_SOURCES.get(kernel, ())
     for f, h in rec.get("source_sha256_16", {}).items():
+        if f not in deps:
+            continue
         src = os.path.join(ROOT, "paper_1608_00802_amd", "csrc", f)
         if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != h:
             return None
