@@ -145,7 +145,7 @@ struct Tiles {
 // so a transform makes one trip through LDS (the exchange between the two
 // factors) instead of one per radix-4 stage.  The y and x passes use this
 // form; the z passes (with their real-data packing) use fft_rows.
-constexpr int kRegBlock = 128;   // threads per block of the register-FFT passes
+constexpr int kRegBlock = 128;   // threads per block of the register-FFT y passes
 
 template <int L>
 struct Split {
@@ -271,7 +271,7 @@ __global__ void __launch_bounds__(kBlock) k_r2c_z(const void* __restrict__ in,
 }
 
 // ---------------------------------------------------------------- passes 2-4
-// Register-FFT versions of passes 2-4 (kRegBlock threads).  The y pass
+// Register-FFT versions of passes 2-4.  The y pass
 // reads each row's F1-strided elements straight into registers and writes
 // the result from registers; the x pass keeps the forward transform's output
 // in registers for the Green's function and the inverse transform's first
@@ -283,8 +283,14 @@ struct RegTiles {
   static constexpr int RMAX = R1 > R2 ? R1 : R2;
   static constexpr int RY0 = kRegBlock / R2;                       // y-pass rows per block
   static constexpr int RY = RY0 < N ? RY0 : N;
-  static constexpr int TC0 = (kRegBlock / RMAX > 8) ? kRegBlock / RMAX : 8;
+  // x pass: 64 threads and 4 columns up to N = 256 (36 against 46 us per
+  // pass at 256^3 with 128 threads and 8 columns), 128 and 8 above (380
+  // against 466 us at 512^3); the blocks that share a 128-byte line of a
+  // column run are grouped on one XCD
+  static constexpr int XT = N <= 256 ? 64 : 128;                   // x-pass threads per block
+  static constexpr int TC0 = N <= 256 ? ((XT / RMAX > 4) ? XT / RMAX : 4) : 8;
   static constexpr int TC = TC0 < N ? TC0 : N;                     // x-pass columns per block
+  static constexpr int XG = TC < 16 ? 16 / TC : 1;                 // XCD group
 };
 
 template <int LOGN, bool INV>
@@ -341,7 +347,7 @@ __global__ void __launch_bounds__(kRegBlock) k_fft_y_reg(float2* __restrict__ sp
 }
 
 template <int LOGN>
-__global__ void __launch_bounds__(kRegBlock) k_fft_x_green_reg(float2* __restrict__ spec,
+__global__ void __launch_bounds__(RegTiles<1 << LOGN>::XT) k_fft_x_green_reg(float2* __restrict__ spec,
                                                                const float2* __restrict__ tw,
                                                                const float* __restrict__ s2,
                                                                float green_scale, Batch bt) {
@@ -349,17 +355,18 @@ __global__ void __launch_bounds__(kRegBlock) k_fft_x_green_reg(float2* __restric
   constexpr int N = 1 << LOGN;
   constexpr int R1 = Split<N>::R1, R2 = Split<N>::R2;
   constexpr int TC = RegTiles<N>::TC;
+  constexpr int XT = RegTiles<N>::XT;
   // forward exchange ex[c][n2][k1] (k1 < R1, padded), inverse ex[c][k1][k1']
   // (k1' < R2, padded); one buffer, the larger of the two
   constexpr int XF = R2 * (R1 + 1), XI = R1 * (R2 + 1);
   constexpr int XS = XF > XI ? XF : XI;
   constexpr int NA = TC * R2, NB = TC * R1;   // items: first factor (R1 values) / second (R2 values)
-  constexpr int PA = (NA + kRegBlock - 1) / kRegBlock, PB = (NB + kRegBlock - 1) / kRegBlock;
+  constexpr int PA = (NA + XT - 1) / XT, PB = (NB + XT - 1) / XT;
   __shared__ float2 ex[TC * XS];
   __shared__ float2 tws[N];
   __shared__ float s2s[N];
   const int tid = threadIdx.x;
-  const int b = (int)xcd_block(blockIdx.x, gridDim.x, xcd_group(FDM_XCD_FFTX, gridDim.x));
+  const int b = (int)xcd_block(blockIdx.x, gridDim.x, RegTiles<N>::XG);
   const int kz = b / (N / TC);
   const int y0 = (b % (N / TC)) * TC;
   auto at = [&](int x, int c) -> float2& { return spec[((size_t)kz * N + x) * N + y0 + c]; };
@@ -367,22 +374,22 @@ __global__ void __launch_bounds__(kRegBlock) k_fft_x_green_reg(float2* __restric
   float2 v[PA][R1];
 #pragma unroll
   for (int p = 0; p < PA; ++p) {
-    const int it = tid + p * kRegBlock;
-    if (NA % kRegBlock == 0 || it < NA) {
+    const int it = tid + p * XT;
+    if (NA % XT == 0 || it < NA) {
       const int c = it % TC, n2 = it / TC;
 #pragma unroll
       for (int n1 = 0; n1 < R1; ++n1) v[p][n1] = at(R2 * n1 + n2, c);
     }
   }
-  for (int k = tid; k < N; k += kRegBlock) {
+  for (int k = tid; k < N; k += XT) {
     tws[k] = tw[k];
     s2s[k] = s2[k];
   }
   __syncthreads();
 #pragma unroll
   for (int p = 0; p < PA; ++p) {
-    const int it = tid + p * kRegBlock;
-    if (NA % kRegBlock == 0 || it < NA) {
+    const int it = tid + p * XT;
+    if (NA % XT == 0 || it < NA) {
       const int c = it % TC, n2 = it / TC;
       fft_first<N, R1, false>(v[p], n2, tws);
 #pragma unroll
@@ -396,8 +403,8 @@ __global__ void __launch_bounds__(kRegBlock) k_fft_x_green_reg(float2* __restric
   const float s2z = s2s[kz];
 #pragma unroll
   for (int p = 0; p < PB; ++p) {
-    const int it = tid + p * kRegBlock;
-    if (NB % kRegBlock == 0 || it < NB) {
+    const int it = tid + p * XT;
+    if (NB % XT == 0 || it < NB) {
       const int c = it % TC, k1 = it / TC;
 #pragma unroll
       for (int n2 = 0; n2 < R2; ++n2) u[p][n2] = ex[c * XS + n2 * (R1 + 1) + k1];
@@ -415,8 +422,8 @@ __global__ void __launch_bounds__(kRegBlock) k_fft_x_green_reg(float2* __restric
   __syncthreads();   // every read of the forward exchange is done
 #pragma unroll
   for (int p = 0; p < PB; ++p) {
-    const int it = tid + p * kRegBlock;
-    if (NB % kRegBlock == 0 || it < NB) {
+    const int it = tid + p * XT;
+    if (NB % XT == 0 || it < NB) {
       const int c = it % TC, k1 = it / TC;
 #pragma unroll
       for (int j = 0; j < R2; ++j) ex[c * XS + k1 * (R2 + 1) + j] = u[p][j];
@@ -426,8 +433,8 @@ __global__ void __launch_bounds__(kRegBlock) k_fft_x_green_reg(float2* __restric
   // inverse second factor: item (c, j), j < R2, over k1 < R1: x[j + R2 m]
 #pragma unroll
   for (int p = 0; p < PA; ++p) {
-    const int it = tid + p * kRegBlock;
-    if (NA % kRegBlock == 0 || it < NA) {
+    const int it = tid + p * XT;
+    if (NA % XT == 0 || it < NA) {
       const int c = it % TC, j = it / TC;
 #pragma unroll
       for (int k1 = 0; k1 < R1; ++k1) v[p][k1] = ex[c * XS + k1 * (R2 + 1) + j];
@@ -526,7 +533,7 @@ hipError_t launch_fft_x_green(int logn, float2* spec, const float2* tw, const fl
   {                                                                                 \
     constexpr int N_ = 1 << LN;                                                     \
     dim3 g((N_ / 2 + 1) * (N_ / RegTiles<N_>::TC), bt.count);                       \
-    hipLaunchKernelGGL((k_fft_x_green_reg<LN>), g, dim3(kRegBlock), 0, s, spec, tw, s2,  \
+    hipLaunchKernelGGL((k_fft_x_green_reg<LN>), g, dim3(RegTiles<N_>::XT), 0, s, spec, tw, s2, \
                        green_scale, bt);                                            \
   }
   FDM_LOGN_SWITCH(logn, L_)

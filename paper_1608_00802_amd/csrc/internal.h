@@ -101,15 +101,11 @@ __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned used, unsigne
   const unsigned r = b % span;
   return b - r + (r % kXcds) * group + r / kXcds;
 }
-// x-pass FFT blocks two at a time (the two halves of each 128-byte line of a
-// column run), tiled launches eight chunks at a time (a row of tiles along z
-// at N = 256: their windows share halo lines).  Measured at 256^3: 5 us less
-// per x-pass, 4-6 us less per gather; one contiguous run per XCD made the
-// gather of a clustered state 15% slower (uneven work per XCD) and the Q
-// stencil 8% slower.
-#ifndef FDM_XCD_FFTX
-#define FDM_XCD_FFTX 2        // -1: one contiguous run per XCD, else group size (0: off)
-#endif
+// Tiled launches take eight chunks at a time (a row of tiles along z at
+// N = 256: their windows share halo lines): 4-6 us less per gather at 256^3;
+// one contiguous run per XCD made the gather of a clustered state 15%
+// slower (uneven work per XCD) and the Q stencil 8% slower.  (The x pass of
+// the FFT groups its blocks by the 128-byte lines they share.)
 #ifndef FDM_XCD_TILES
 #define FDM_XCD_TILES 8
 #endif
