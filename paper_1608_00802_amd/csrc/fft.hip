@@ -229,24 +229,44 @@ __global__ void __launch_bounds__(kBlock) k_r2c_z(const void* __restrict__ in,
   const int x = blockIdx.x / (N / TZ);
   const int y0 = (blockIdx.x % (N / TZ)) * TZ;
   for (int k = tid; k < N; k += kBlock) tws[k] = tw[k];
-  for (int idx = tid; idx < TZ * H; idx += kBlock) {
-    const int r = idx / H, n = idx % H;
-    const size_t cell = ((size_t)x * N + y0 + r) * N + 2 * n;
-    float2 d;
-    if constexpr (SRC == kSrcMass64) {
-      const longlong2 m = *reinterpret_cast<const longlong2*>((const long long*)in + cell);
-      d.x = (float)((double)(m.x - conv.mbar) / conv.dmbar);
-      d.y = (float)((double)(m.y - conv.mbar) / conv.dmbar);
-      *reinterpret_cast<float2*>(delta_out + cell) = d;
-    } else if constexpr (SRC == kSrcAcc32) {
-      const float2 a = *reinterpret_cast<const float2*>((const float*)in + cell);
-      d.x = a.x * conv.acc_norm - 1.0f;
-      d.y = a.y * conv.acc_norm - 1.0f;
-      *reinterpret_cast<float2*>(delta_out + cell) = d;
-    } else {
-      d = *reinterpret_cast<const float2*>((const float*)in + cell);
+  {
+    // all of a thread's loads are issued before the first is used
+    constexpr int NE = TZ * H;
+    constexpr int PER = (NE + kBlock - 1) / kBlock;
+    longlong2 m[SRC == kSrcMass64 ? PER : 1];
+    float2 a[SRC == kSrcMass64 ? 1 : PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int idx = tid + k * kBlock;
+      if (NE % kBlock == 0 || idx < NE) {
+        const size_t cell = ((size_t)x * N + y0 + idx / H) * N + 2 * (idx % H);
+        if constexpr (SRC == kSrcMass64)
+          m[k] = *reinterpret_cast<const longlong2*>((const long long*)in + cell);
+        else
+          a[k] = *reinterpret_cast<const float2*>((const float*)in + cell);
+      }
     }
-    buf[r * LP + n] = d;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int idx = tid + k * kBlock;
+      if (NE % kBlock == 0 || idx < NE) {
+        const int r = idx / H, n = idx % H;
+        const size_t cell = ((size_t)x * N + y0 + r) * N + 2 * n;
+        float2 d;
+        if constexpr (SRC == kSrcMass64) {
+          d.x = (float)((double)(m[k].x - conv.mbar) / conv.dmbar);
+          d.y = (float)((double)(m[k].y - conv.mbar) / conv.dmbar);
+          *reinterpret_cast<float2*>(delta_out + cell) = d;
+        } else if constexpr (SRC == kSrcAcc32) {
+          d.x = a[k].x * conv.acc_norm - 1.0f;
+          d.y = a[k].y * conv.acc_norm - 1.0f;
+          *reinterpret_cast<float2*>(delta_out + cell) = d;
+        } else {
+          d = a[k];
+        }
+        buf[r * LP + n] = d;
+      }
+    }
   }
   __syncthreads();
   fft_rows<H, TZ, kBlock, 2, false>(buf, tws);
@@ -465,9 +485,22 @@ __global__ void __launch_bounds__(kBlock) k_c2r_z(const float2* __restrict__ spe
   const int x = blockIdx.x / (N / TZ);
   const int y0 = (blockIdx.x % (N / TZ)) * TZ;
   for (int k = tid; k < N; k += kBlock) tws[k] = tw[k];
-  for (int idx = tid; idx < (H + 1) * TZ; idx += kBlock) {
-    const int kz = idx / TZ, r = idx % TZ;
-    buf[r * LP + kz] = spec[((size_t)kz * N + x) * N + y0 + r];
+  {
+    // all of a thread's loads are issued before the first is used
+    constexpr int NE = (H + 1) * TZ;
+    constexpr int PER = (NE + kBlock - 1) / kBlock;
+    float2 v[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int idx = tid + k * kBlock;
+      if (NE % kBlock == 0 || idx < NE)
+        v[k] = spec[((size_t)(idx / TZ) * N + x) * N + y0 + idx % TZ];
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int idx = tid + k * kBlock;
+      if (NE % kBlock == 0 || idx < NE) buf[(idx % TZ) * LP + idx / TZ] = v[k];
+    }
   }
   __syncthreads();
   // pack: E = (X_k + conj X_{H-k})/2, O = (X_k - conj X_{H-k}) conj(w^k)/2,

@@ -264,11 +264,31 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather_tiled(void* __restrict_
     if (pk < hi) load_particle(pos, vel, np, pk, raw_n[k], vin_n[k]);
   }
   const int ox = (t / (NTY * NTZ)) * TX, oy = ((t / NTZ) % NTY) * TY, oz = (t % NTZ) * TZ;
-  for (int c = threadIdx.x; c < WX * WY * WZ; c += kGatherBlock) {
-    const int lx = c / (WY * WZ), ly = (c / WZ) % WY, lz = c % WZ;
-    const size_t idx = ((size_t)((ox - 1 - HG + lx) & MASK) * N +
-                        ((oy - 1 - HG + ly) & MASK)) * N + ((oz - 1 - HG + lz) & MASK);
-    win[c] = mesh_f<LOGN, HAS_Q>(phi, q, gc, idx);
+  {
+    // all of a thread's window loads are issued before the first is used
+    constexpr int WN = WX * WY * WZ;
+    constexpr int WPER = (WN + kGatherBlock - 1) / kGatherBlock;
+    float wphi[WPER], wq[HAS_Q ? WPER : 1];
+#pragma unroll
+    for (int k = 0; k < WPER; ++k) {
+      const int c = threadIdx.x + k * kGatherBlock;
+      if (WN % kGatherBlock == 0 || c < WN) {
+        const int lx = c / (WY * WZ), ly = (c / WZ) % WY, lz = c % WZ;
+        const size_t idx = ((size_t)((ox - 1 - HG + lx) & MASK) * N +
+                            ((oy - 1 - HG + ly) & MASK)) * N + ((oz - 1 - HG + lz) & MASK);
+        wphi[k] = phi[idx];
+        if constexpr (HAS_Q) wq[k] = q[idx];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < WPER; ++k) {
+      const int c = threadIdx.x + k * kGatherBlock;
+      if (WN % kGatherBlock == 0 || c < WN) {
+        // the rounding of mesh_f
+        if constexpr (HAS_Q) win[c] = fmaf(gc.fq, wq[k], gc.fg * wphi[k]);
+        else win[c] = gc.fg * wphi[k];
+      }
+    }
   }
   if constexpr (DEP)
     for (int c = threadIdx.x; c < DX * DY * DZ; c += kGatherBlock) dacc[c] = (T)0;
@@ -337,13 +357,23 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather_tiled(void* __restrict_
                                             8 * ((size_t)N * N * N)) +
                     (blockIdx.x % kStraySlices) * kStrayStride,
                 n_stray);
-    for (int c = threadIdx.x; c < DX * DY * DZ; c += kGatherBlock) {
-      const T v = dacc[c];
-      if (v != (T)0) {
+    // all of a thread's window cells are read before the first atomic
+    constexpr int DN = DX * DY * DZ;
+    constexpr int DPER = (DN + kGatherBlock - 1) / kGatherBlock;
+    T dv[DPER];
+#pragma unroll
+    for (int k = 0; k < DPER; ++k) {
+      const int c = threadIdx.x + k * kGatherBlock;
+      dv[k] = (DN % kGatherBlock == 0 || c < DN) ? dacc[c] : (T)0;
+    }
+#pragma unroll
+    for (int k = 0; k < DPER; ++k) {
+      const int c = threadIdx.x + k * kGatherBlock;
+      if (dv[k] != (T)0) {
         const int lx = c / (DY * DZ), ly = (c / DZ) % DY, lz = c % DZ;
         const size_t cell = ((size_t)((ox - HD + lx) & MASK) * N + ((oy - HD + ly) & MASK)) * N +
                             ((oz - HD + lz) & MASK);
-        add_global(&mass[cell], v);
+        add_global(&mass[cell], dv[k]);
       }
     }
   }
