@@ -223,6 +223,9 @@ __global__ void __launch_bounds__(kBlock) k_qpot_tiled(const float* __restrict__
   };
   double wsum = 0.0, usum = 0.0;
   float s_prev = s_of<FIXED>(delta[((size_t)((x0 - 1) & MASK) * N + y) * N + z], qc);
+  // phi of the own column, loaded one plane ahead (psi and energy outputs)
+  float phi_cur = 0.0f;
+  if constexpr (OUT != kOutQ) phi_cur = phi[((size_t)x0 * N + y) * N + z];
   fetch(x0);
   commit(pl[0], 0);
   fetch(x0 + 1);
@@ -237,6 +240,9 @@ __global__ void __launch_bounds__(kBlock) k_qpot_tiled(const float* __restrict__
     float* nb = pl[nbi];
     commit(nb, nbi);                          // plane x + 1
     if (x + 2 <= x0 + QX) fetch(x + 2);
+    float phi_next = 0.0f;
+    if constexpr (OUT != kOutQ)
+      if (x + 1 < x0 + QX) phi_next = phi[((size_t)(x + 1) * N + y) * N + z];
     __syncthreads();
     const bool near_next = plane_near(nbi);
     const float s_next = nb[cc];
@@ -279,11 +285,11 @@ __global__ void __launch_bounds__(kBlock) k_qpot_tiled(const float* __restrict__
       qv = qc.coef * lap / s_cur;
     }
     if constexpr (OUT == kOutPsi)
-      q[i] = fmaf(qc.psi_q, qv, qc.psi_g * phi[i]);
+      q[i] = fmaf(qc.psi_q, qv, qc.psi_g * phi_cur);
     else
       q[i] = qv;
     if constexpr (OUT == kOutEnergy) {
-      wsum += (double)delta[i] * (double)phi[i];
+      wsum += (double)delta[i] * (double)phi_cur;
       const double e0 = (double)(s_next - s_cur), e1 = (double)(sy_cur - s_cur),
                    e2 = (double)(sz_cur - s_cur);
       usum += e0 * e0 + e1 * e1 + e2 * e2;
@@ -295,6 +301,7 @@ __global__ void __launch_bounds__(kBlock) k_qpot_tiled(const float* __restrict__
     sz_cur = sz_next;
     d_prev = d_c;
     near_cur = near_next;
+    phi_cur = phi_next;
   }
   if constexpr (OUT == kOutEnergy) {
     __shared__ double red[kBlock / 64];
