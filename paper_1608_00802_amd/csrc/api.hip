@@ -564,6 +564,10 @@ namespace {
 
 constexpr double kSortBalance = 0.02;
 constexpr int kSortIntervalMax = 32;
+#ifndef FDM_WIDE_INTERVAL
+#define FDM_WIDE_INTERVAL 8
+#endif
+constexpr int kWideInterval = FDM_WIDE_INTERVAL;   // 0: never the wide windows
 
 pm_status sample_sort_stat(pm_ctx* c) {
   if (!c->sorted) return PM_OK;
@@ -574,6 +578,7 @@ pm_status sample_sort_stat(pm_ctx* c) {
     }
     if (hipEventCreateWithFlags(&c->ev_stat, hipEventDisableTiming) != hipSuccess)
       return PM_EDEVICE;
+    if (c->fixed) PM_TRY(dev(preload_wide(c->logn)));
   }
   PM_TRY(dev(hipMemcpyAsync(c->h_stat, static_cast<char*>(c->mass) + 8 * c->ncell, kStrayBytes,
                             hipMemcpyDeviceToHost, c->stream)));
@@ -709,10 +714,14 @@ pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int
     gc.fd_units = drift(c->p, t0, t1) * fdu;
     // gather + kick + drift, fused with the deposit of the drifted particles
     PM_TRY(timed(c, kcFill, [&] { return launch_fill_zero(c->mass, 8 * c->ncell + kStrayBytes, c->stream); }));
+    // once the particles have moved since the sort, a state whose adaptive
+    // interval is short (strays are frequent) takes the wider windows
+    const bool wide = sort_auto && c->sorted && c->since_sort > 0 &&
+                      c->sort_interval <= kWideInterval;
     PM_TRY(timed(c, kcGatherKD, [&] {
       return launch_gather(c->fixed, c->has_q && !psi, true, c->logn, cur_pos, cur_vel,
                            psi ? c->q : c->phi, c->q, c->np, gc,
-                           c->sorted ? &c->tmap : nullptr, c->mass, c->stream);
+                           c->sorted ? &c->tmap : nullptr, c->mass, c->stream, Batch(), wide);
     }));
     ++c->since_sort;
     if (sort_auto && !c->stat_pending) PM_TRY(sample_sort_stat(c));

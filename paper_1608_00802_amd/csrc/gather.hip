@@ -210,7 +210,9 @@ __global__ void __launch_bounds__(kBlock) k_gather(void* __restrict__ pos,
 // is staged once for the tile's window (cells -1 .. T+1 around the tile) in
 // LDS; particles still inside their tile read their 32 nodes from LDS,
 // particles that left it read the mesh directly.
-template <int LOGN, bool FIXED, bool HAS_Q, int MODE, bool DEP>
+// WIDE: a one-cell larger gather window and a two-cell deposit halo, for
+// steps whose particles have moved since the sort in a clustered state.
+template <int LOGN, bool FIXED, bool HAS_Q, int MODE, bool DEP, int WIDE = 0>
 __global__ void __launch_bounds__(kGatherBlock) k_gather_tiled(void* __restrict__ pos,
                                                          float* __restrict__ vel,
                                                          const float* __restrict__ phi,
@@ -241,7 +243,7 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather_tiled(void* __restrict_
   constexpr int N = 1 << LOGN;
   constexpr int MASK = N - 1;
   constexpr int TX = 1 << tile_lx(LOGN), TY = 1 << tile_ly(LOGN), TZ = 1 << tile_lz(LOGN);
-  constexpr int HG = kGatherHalo, HD = kDepHalo;
+  constexpr int HG = WIDE ? 1 : kGatherHalo, HD = WIDE ? 2 : kDepHalo;
   // F window: cells o - 1 - HG .. o + T + 1 + HG; deposit window: o - HD .. o + T + HD
   constexpr int WX = TX + 3 + 2 * HG, WY = TY + 3 + 2 * HG, WZ = TZ + 3 + 2 * HG;
   constexpr int NTY = N / TY, NTZ = N / TZ;
@@ -427,14 +429,30 @@ static void launch_mode(bool fixed, bool has_q, dim3 g, hipStream_t s, void* pos
                        phi, q, np, gc, acc, mass, bt);
 }
 
+template <int LN>
+static void launch_wide(bool has_q, hipStream_t s, void* pos, float* vel, const float* phi,
+                        const float* q, int64_t np, const TileMap& tm, const GatherConst& gc,
+                        void* mass, const Batch& bt) {
+  const dim3 g(tiled_grid(np, tm.tiles), bt.count);
+  if (has_q)
+    hipLaunchKernelGGL((k_gather_tiled<LN, true, true, kKickDrift, true, 1>), g,
+                       dim3(kGatherBlock), 0, s, pos, vel, phi, q, np, tm, gc, nullptr, mass, bt);
+  else
+    hipLaunchKernelGGL((k_gather_tiled<LN, true, false, kKickDrift, true, 1>), g,
+                       dim3(kGatherBlock), 0, s, pos, vel, phi, q, np, tm, gc, nullptr, mass, bt);
+}
+
 hipError_t launch_gather(bool fixed, bool has_q, bool drift, int logn, void* pos, float* vel,
                          const float* phi, const float* q, int64_t np, const GatherConst& gc,
-                         const TileMap* tm, void* deposit_mass, hipStream_t s, const Batch& bt) {
+                         const TileMap* tm, void* deposit_mass, hipStream_t s, const Batch& bt,
+                         bool wide) {
   const dim3 g(grid_particles(np));
   const bool dep = drift && deposit_mass != nullptr;
 #define L_(LN)                                                                                 \
   {                                                                                            \
-    if (tm && dep)                                                                             \
+    if (tm && dep && wide && fixed)                                                            \
+      launch_wide<LN>(has_q, s, pos, vel, phi, q, np, *tm, gc, deposit_mass, bt);              \
+    else if (tm && dep)                                                                        \
       launch_mode_tiled<LN, kKickDrift, true>(fixed, has_q, s, pos, vel, phi, q, np, *tm, gc,  \
                                               nullptr, deposit_mass, bt);                      \
     else if (tm && drift)                                                                      \
@@ -456,6 +474,24 @@ hipError_t launch_gather(bool fixed, bool has_q, bool drift, int logn, void* pos
   FDM_LOGN_SWITCH(logn, L_)
 #undef L_
   return hipGetLastError();
+}
+
+// Query the wide-window kernels once, so that their first use inside a step
+// loop does not also load them (a one-time stall of tens of ms otherwise).
+hipError_t preload_wide(int logn) {
+  hipFuncAttributes attr;
+  hipError_t e = hipSuccess;
+#define L_(LN)                                                                                   \
+  {                                                                                              \
+    e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(                               \
+                                        &k_gather_tiled<LN, true, true, kKickDrift, true, 1>));   \
+    if (e == hipSuccess)                                                                         \
+      e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(                             \
+                                          &k_gather_tiled<LN, true, false, kKickDrift, true, 1>)); \
+  }
+  FDM_LOGN_SWITCH(logn, L_)
+#undef L_
+  return e;
 }
 
 hipError_t launch_force(bool fixed, bool has_q, int logn, const void* pos, const float* phi,

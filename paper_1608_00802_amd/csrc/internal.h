@@ -280,10 +280,13 @@ hipError_t launch_reduce(const double* partials, int nblocks, int ncomp, double*
                          hipStream_t s, const Batch& bt = Batch());
 
 // ---- gather.hip
+// wide (fixed point, fused deposit on a sorted context): the larger windows
+// of k_gather_tiled's WIDE form
 hipError_t launch_gather(bool fixed, bool has_q, bool drift, int logn, void* pos,
                          float* vel, const float* phi, const float* q, int64_t np,
                          const GatherConst& gc, const TileMap* tm, void* deposit_mass,
-                         hipStream_t s, const Batch& bt = Batch());
+                         hipStream_t s, const Batch& bt = Batch(), bool wide = false);
+hipError_t preload_wide(int logn);
 hipError_t launch_force(bool fixed, bool has_q, int logn, const void* pos,
                         const float* phi, const float* q, int64_t np, float fg, float fq,
                         float* acc, hipStream_t s);
