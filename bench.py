@@ -154,10 +154,10 @@ def copy_calibration(nbytes=1 << 30, reps=3):
 
 # rocprofv3 kernel-name prefix of each kernel family in the traffic summary
 # (inside a call the gather reads psi alone and the stencil writes psi)
-TRAFFIC_KERNEL = {"gather_kick_drift": "k_gather_tiled<8, true, false, 1, true>",
+TRAFFIC_KERNEL = {"gather_kick_drift": "k_gather_tiled<8, true, false, 1, true, 0>",
                   "deposit": "k_deposit_tiled<8, true>", "qpot": "k_qpot_tiled<8, true, 2>",
-                  "r2c_z": "k_r2c_z<8, 0>", "fft_y": "k_fft_y<8, false>",
-                  "fft_x_green": "k_fft_x_green<8>", "fft_y_inv": "k_fft_y<8, true>",
+                  "r2c_z": "k_r2c_z<8, 0>", "fft_y": "k_fft_y_reg<8, false>",
+                  "fft_x_green": "k_fft_x_green_reg<8>", "fft_y_inv": "k_fft_y_reg<8, true>",
                   "c2r_z": "k_c2r_z<8>"}
 
 
