@@ -88,6 +88,7 @@ struct pm_ctx {
   bool stat_pending = false;
   int stat_age = 0;             // steps since the sort at the sampled step
   int sort_interval = 10;
+  bool wide_windows = false;    // aged steps take the wide gather windows
   int since_sort = 1 << 30;     // steps since the last sort
 };
 
@@ -568,6 +569,10 @@ constexpr int kSortIntervalMax = 32;
 #define FDM_WIDE_INTERVAL 8
 #endif
 constexpr int kWideInterval = FDM_WIDE_INTERVAL;   // 0: never the wide windows
+#ifndef FDM_WIDE_EXTRA
+#define FDM_WIDE_EXTRA 1
+#endif
+constexpr int kWideExtra = FDM_WIDE_EXTRA;
 
 pm_status sample_sort_stat(pm_ctx* c) {
   if (!c->sorted) return PM_OK;
@@ -600,6 +605,11 @@ void poll_sort_stat(pm_ctx* c) {
     const double l = cbrt(kSortBalance * k * k / f);
     interval = l < 1.0 ? 1 : (l > kSortIntervalMax ? kSortIntervalMax : (int)l);
   }
+  // Strays are counted against the narrow windows.  Where they set a short
+  // interval, the steps after the first since a sort take the wide windows,
+  // which absorb about one more step of motion: one step more between sorts.
+  c->wide_windows = interval <= kWideInterval;
+  if (c->wide_windows) interval = std::min(interval + kWideExtra, kSortIntervalMax);
   c->sort_interval = interval;
 }
 
@@ -716,8 +726,7 @@ pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int
     PM_TRY(timed(c, kcFill, [&] { return launch_fill_zero(c->mass, 8 * c->ncell + kStrayBytes, c->stream); }));
     // once the particles have moved since the sort, a state whose adaptive
     // interval is short (strays are frequent) takes the wider windows
-    const bool wide = sort_auto && c->sorted && c->since_sort > 0 &&
-                      c->sort_interval <= kWideInterval;
+    const bool wide = sort_auto && c->sorted && c->wide_windows && c->since_sort > 0;
     PM_TRY(timed(c, kcGatherKD, [&] {
       return launch_gather(c->fixed, c->has_q && !psi, true, c->logn, cur_pos, cur_vel,
                            psi ? c->q : c->phi, c->q, c->np, gc,

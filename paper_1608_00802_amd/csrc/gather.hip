@@ -348,8 +348,14 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather_tiled(void* __restrict_
       } else {
         deposit_global<LOGN>(static_cast<T*>(mass_v), jx, jy, jz, w);
       }
-      // count strays: one LDS atomic per wave
-      const unsigned long long m = __ballot(!inside);
+      // count strays (always against the narrow deposit window, so that the
+      // sort interval chosen from them does not depend on the window used):
+      // one LDS atomic per wave
+      constexpr int HN = kDepHalo;
+      const bool inside_n = ((jx - ox + HN) & MASK) < TX + 2 * HN &&
+                            ((jy - oy + HN) & MASK) < TY + 2 * HN &&
+                            ((jz - oz + HN) & MASK) < TZ + 2 * HN;
+      const unsigned long long m = __ballot(!inside_n);
       if (m && (threadIdx.x & 63) == __ffsll((long long)__ballot(1)) - 1)
         atomicAdd(&n_stray, (unsigned)__popcll(m));
     }
