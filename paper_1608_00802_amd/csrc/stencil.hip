@@ -122,6 +122,9 @@ __global__ void __launch_bounds__(kBlock) k_qpot(const float* __restrict__ delta
 // read about (QY+2)(QZ+2)/(QY QZ) times instead of once per stencil point.
 // The loads of plane x + 2 are issued before plane x is computed.
 constexpr int QY = 8, QZ = 32, QX = 16;
+#ifndef FDM_XCD_QPOT
+#define FDM_XCD_QPOT 8   // a z-row of blocks per XCD at a time (256^3: 64 -> 62 us)
+#endif
 static_assert(QY * QZ == kBlock, "one cell per thread and plane");
 
 template <bool FIXED>
@@ -166,7 +169,7 @@ __global__ void __launch_bounds__(kBlock) k_qpot_tiled(const float* __restrict__
   // alternating by plane)
   __shared__ uint32_t nflag[2][kBlock / 64];
   const int nby = N / QY, nbz = N / QZ;
-  const int b = (int)blockIdx.x;
+  const int b = (int)xcd_block(blockIdx.x, gridDim.x, FDM_XCD_QPOT);
   const int bz = b % nbz, by = (b / nbz) % nby, bx = b / (nbz * nby);
   const int y0 = by * QY, z0 = bz * QZ, x0 = bx * QX;
   const int ty = threadIdx.x / QZ, tz = threadIdx.x % QZ;
