@@ -748,11 +748,15 @@ pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int
   gc.fg = (float)close.g;
   gc.fq = (float)close.q;
   gc.fd_units = 0.0;
+  // closing half-kick; if the particles ended in the workspace copies, the
+  // same pass writes them back to the caller's arrays
+  const bool back = cur_pos != d_pos;
   PM_TRY(timed(c, kcKick, [&] {
     return launch_gather(c->fixed, c->has_q, false, c->logn, cur_pos, cur_vel, c->phi, c->q,
-                         c->np, gc, c->sorted ? &c->tmap : nullptr, nullptr, c->stream);
+                         c->np, gc, c->sorted ? &c->tmap : nullptr, nullptr, c->stream, Batch(),
+                         false, back ? d_pos : nullptr, back ? d_vel : nullptr);
   }));
-  if (cur_pos != d_pos) PM_TRY(copy_particles(c, d_pos, d_vel, cur_pos, cur_vel));
+  if (back && !c->sorted) PM_TRY(copy_particles(c, d_pos, d_vel, cur_pos, cur_vel));
   c->fields_at_pos = true;
   return PM_OK;
 }

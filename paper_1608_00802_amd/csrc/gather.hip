@@ -23,7 +23,10 @@
 
 namespace fdm {
 
-enum GatherMode : int { kKick = 0, kKickDrift = 1, kForce = 2 };
+// kKickCopy: kick, writing the velocities to `acc` and copying the position
+// words to `pos_out` (the closing half-kick of a call whose particles ended in
+// the workspace copies: kick and copy back in one pass).
+enum GatherMode : int { kKick = 0, kKickDrift = 1, kForce = 2, kKickCopy = 3 };
 
 // Position of one particle from its three 32-bit position words (fixed-point
 // units, or float bits): integer cell and fraction along each axis.
@@ -109,11 +112,17 @@ __device__ __forceinline__ void push(void* __restrict__ pos, float* __restrict__
                                      float* __restrict__ acc, int64_t np, int64_t p,
                                      const float g[3], const float vin[3], const uint32_t u[3],
                                      const float xf[3], double fd_units, uint32_t unew[3],
-                                     float xnew[3]) {
+                                     float xnew[3], void* __restrict__ pos_out = nullptr) {
   constexpr int N = 1 << LOGN;
   if constexpr (MODE == kForce) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) acc[d * np + p] = g[d];
+  } else if constexpr (MODE == kKickCopy) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      acc[d * np + p] = vin[d] + g[d];
+      static_cast<uint32_t*>(pos_out)[d * np + p] = FIXED ? u[d] : __float_as_uint(xf[d]);
+    }
   } else {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -196,7 +205,7 @@ __global__ void __launch_bounds__(kBlock) k_gather(void* __restrict__ pos,
     }, g);
     uint32_t unew[3];
     float xnew[3];
-    push<LOGN, FIXED, MODE>(pos, vel, acc, np, p, g, vin, u, xf, gc.fd_units, unew, xnew);
+    push<LOGN, FIXED, MODE>(pos, vel, acc, np, p, g, vin, u, xf, gc.fd_units, unew, xnew, mass_v);
     if constexpr (DEP) {
       int jx, jy, jz;
       T w[8];
@@ -333,7 +342,7 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather_tiled(void* __restrict_
     }
     uint32_t unew[3];
     float xnew[3];
-    push<LOGN, FIXED, MODE>(pos, vel, acc, np, p, g, vin, u, xf, gc.fd_units, unew, xnew);
+    push<LOGN, FIXED, MODE>(pos, vel, acc, np, p, g, vin, u, xf, gc.fd_units, unew, xnew, mass_v);
     if constexpr (DEP) {
       int jx, jy, jz;
       T w[8];
@@ -451,12 +460,16 @@ static void launch_wide(bool has_q, hipStream_t s, void* pos, float* vel, const 
 hipError_t launch_gather(bool fixed, bool has_q, bool drift, int logn, void* pos, float* vel,
                          const float* phi, const float* q, int64_t np, const GatherConst& gc,
                          const TileMap* tm, void* deposit_mass, hipStream_t s, const Batch& bt,
-                         bool wide) {
+                         bool wide, void* pos_out, float* vel_out) {
   const dim3 g(grid_particles(np));
   const bool dep = drift && deposit_mass != nullptr;
+  const bool copy = !drift && tm && pos_out && vel_out;
 #define L_(LN)                                                                                 \
   {                                                                                            \
-    if (tm && dep && wide && fixed)                                                            \
+    if (copy)                                                                                  \
+      launch_mode_tiled<LN, kKickCopy, false>(fixed, has_q, s, pos, vel, phi, q, np, *tm, gc,  \
+                                              vel_out, pos_out, bt);                           \
+    else if (tm && dep && wide && fixed)                                                       \
       launch_wide<LN>(has_q, s, pos, vel, phi, q, np, *tm, gc, deposit_mass, bt);              \
     else if (tm && dep)                                                                        \
       launch_mode_tiled<LN, kKickDrift, true>(fixed, has_q, s, pos, vel, phi, q, np, *tm, gc,  \

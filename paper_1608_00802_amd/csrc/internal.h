@@ -281,11 +281,14 @@ hipError_t launch_reduce(const double* partials, int nblocks, int ncomp, double*
 
 // ---- gather.hip
 // wide (fixed point, fused deposit on a sorted context): the larger windows
-// of k_gather_tiled's WIDE form
+// of k_gather_tiled's WIDE form.  pos_out, vel_out (kick without drift on a
+// sorted context): write the kicked velocities and a copy of the positions
+// there instead of in place.
 hipError_t launch_gather(bool fixed, bool has_q, bool drift, int logn, void* pos,
                          float* vel, const float* phi, const float* q, int64_t np,
                          const GatherConst& gc, const TileMap* tm, void* deposit_mass,
-                         hipStream_t s, const Batch& bt = Batch(), bool wide = false);
+                         hipStream_t s, const Batch& bt = Batch(), bool wide = false,
+                         void* pos_out = nullptr, float* vel_out = nullptr);
 hipError_t preload_wide(int logn);
 hipError_t launch_force(bool fixed, bool has_q, int logn, const void* pos,
                         const float* phi, const float* q, int64_t np, float fg, float fq,
