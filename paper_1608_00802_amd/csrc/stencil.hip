@@ -25,6 +25,23 @@ namespace fdm {
 __device__ __forceinline__ float sqrt_hw(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ float rcp_hw(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// FP64 square root and reciprocal for the near-empty path: the hardware
+// single-precision estimate refined by two Newton steps in FP64 (relative
+// error a few 1e-16 for the positive normal arguments used here), several
+// times cheaper than the correctly rounded library forms.
+__device__ __forceinline__ double sqrt_d(double r) {
+  double y = (double)__builtin_amdgcn_rsqf((float)r);   // ~1/sqrt(r), single precision
+  y = y * (1.5 - 0.5 * r * y * y);
+  y = y * (1.5 - 0.5 * r * y * y);
+  return r * y;
+}
+__device__ __forceinline__ double rcp_d(double x) {
+  double y = (double)__builtin_amdgcn_rcpf((float)x);   // ~1/x, single precision
+  y = y * (2.0 - x * y);
+  y = y * (2.0 - x * y);
+  return y;
+}
+
 __device__ __forceinline__ double block_sum(double v, double* red) {
   // wave64 shuffle reduction, then across the block's waves through LDS
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -88,11 +105,11 @@ __global__ void __launch_bounds__(kBlock) k_qpot(const float* __restrict__ delta
       auto sd = [&](size_t j) {
         double r = (double)mass[j] * qc.inv_mbar;
         r = r > qc.floor_d ? r : qc.floor_d;
-        return sqrt(r);
+        return sqrt_d(r);
       };
       const double c = sd(i);
       const double lapd = ((sd(xp) + sd(xm)) + (sd(yp) + sd(ym)) + (sd(zp) + sd(zm))) - 6.0 * c;
-      qv = (float)(qc.coef_d * lapd / c);
+      qv = (float)(qc.coef_d * lapd * rcp_d(c));
     }
   } else {
     auto sfun = [&](float d) {
@@ -225,7 +242,7 @@ __global__ void __launch_bounds__(kBlock) k_qpot_tiled(const float* __restrict__
   auto sd = [&](size_t j) {
     double r = (double)mass[j] * qc.inv_mbar;
     r = r > qc.floor_d ? r : qc.floor_d;
-    return sqrt(r);
+    return sqrt_d(r);
   };
   const int cc = (ty + 1) * PZ + tz + 1;
   auto inplane = [&](const float* buf) {
@@ -288,7 +305,7 @@ __global__ void __launch_bounds__(kBlock) k_qpot_tiled(const float* __restrict__
           if (x == x0) d_prev = sd(((size_t)((x0 - 1) & MASK) * N + y) * N + z);
           const double d_next = sd(((size_t)((x + 1) & MASK) * N + y) * N + z);
           const double lapd = ((d_next + d_prev) + (d_yp + d_ym) + (d_zp + d_zm)) - 6.0 * c0;
-          qv = (float)(qc.coef_d * lapd / c0);
+          qv = (float)(qc.coef_d * lapd * rcp_d(c0));
         }
       }
     } else {
