@@ -438,20 +438,23 @@ def test_sorted_steps_vs_oracle(pm, gpu):
     assert rel_l2(vel.cpu().numpy().T, vo[idn]) < 1e-5
 
 
-def test_step_sort_every_flag(pm, gpu):
+@pytest.mark.parametrize("precision", [1, 0])
+def test_step_sort_every_flag(pm, gpu, precision):
     """PM_SORT_EVERY inside pm_step evolves the same particle set as the
     unsorted run: order-independent comparisons (density field of the final
-    positions, sums of velocity moments)."""
+    positions, sums of velocity moments).  Three sorts in the call leave the
+    particles in the workspace copies, so the closing kick writes them back."""
     import torch
     n = 32
     st = zeldovich_state(n, 10.0, 0.05, seed=2, m_ev=1e-22)
-    lp, _ = cosmo_setup(n, 10.0, 1e-22)
+    lp, _ = cosmo_setup(n, 10.0, 1e-22, precision=precision)
     times = list(0.05 * np.exp(np.arange(9) * 0.01))
+    fp32 = precision == 0
     c1 = _ctx(pm, lp, gpu)
-    p1, v1 = to_device(st, gpu)
+    p1, v1 = to_device(st, gpu, fp32_positions=fp32)
     c1.step(p1, v1, times)
     c2 = _ctx(pm, lp, gpu)
-    p2, v2 = to_device(st, gpu)
+    p2, v2 = to_device(st, gpu, fp32_positions=fp32)
     c2.step(p2, v2, times, flags=pm.PM_SORT_EVERY(3))
     torch.cuda.synchronize()
     d1 = torch.empty(n ** 3, dtype=torch.float32, device=gpu)
@@ -459,11 +462,13 @@ def test_step_sort_every_flag(pm, gpu):
     c1.deposit(p1, d1)
     c2.deposit(p2, d2)
     torch.cuda.synchronize()
-    assert rel_l2(d2.cpu().numpy(), d1.cpu().numpy()) < 1e-6
+    # the float deposit sums in a different order after a sort
+    tol = 1e-5 if fp32 else 1e-6
+    assert rel_l2(d2.cpu().numpy(), d1.cpu().numpy()) < tol
     a = v1.cpu().numpy().astype(np.float64)
     b = v2.cpu().numpy().astype(np.float64)
     for k in (1, 2):
-        assert abs((b ** k).sum() - (a ** k).sum()) < 1e-6 * np.abs(a ** k).sum()
+        assert abs((b ** k).sum() - (a ** k).sum()) < tol * np.abs(a ** k).sum()
 
 
 def _blob_state(n, frac=0.6, sigma=1.5, seed=21, vsig=0.05):
