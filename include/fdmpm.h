@@ -119,7 +119,10 @@ typedef struct pm_ctx pm_ctx;
  * tile's window into pinned host memory (allocated on first use, freed by
  * pm_destroy) and reads it once it has arrived, without waiting: the
  * interval, and so the particle order, may depend on timing, never the
- * state as a set of particles.  Overrides PM_SORT_EVERY. */
+ * state as a set of particles.  Where that count is high (clustered
+ * states), steps after the first since a sort use larger tile windows and
+ * the interval is one step longer; results do not depend on the windows.
+ * Overrides PM_SORT_EVERY. */
 #define PM_SORT_AUTO (1 << 24)
 
 /* Bytes of device workspace a context with these parameters needs.  Pure
