@@ -29,6 +29,8 @@ from .pm import (  # noqa: F401
     kdk_step,
     run,
     energies,
+    kinetic_split,
+    density_rms_diff,
     layzer_irvine_error,
     omega_max,
     timestep,
