@@ -77,7 +77,7 @@ EVOLVE_DLNA = math.log(100.0) / 150.0
 
 
 def run_gpu(st, n, steps, warmup, a_start, kernel_pass=True, sort_every=10, fp32=False,
-            evolve_to=None, box=10.0):
+            evolve_to=None, box=10.0, diag=False):
     """Time `steps` steps (after `warmup`) from a_start; with evolve_to, the
     state is first stepped (untimed) from a_start to evolve_to in steps of
     d ln a = ln(100)/150."""
@@ -133,9 +133,43 @@ def run_gpu(st, n, steps, warmup, a_start, kernel_pass=True, sort_every=10, fp32
                  flags=pm.PM_CONTINUE | sort_flag)
         out["kernels"] = ctx.timing_read()
         ctx.timing(False)
+    if diag:
+        out["diag"] = diag_pass(ctx, pos, vel, p0, times[-1] if kernel_pass else
+                                times[warmup + steps])
     ok = bool(torch.isfinite(vel).all().item())
     out["finite"] = ok
     ctx.close()
+    return out
+
+
+def diag_pass(ctx, pos, vel, p0, a, reps=3):
+    """Grid diagnostics of the state left by the timed steps (after the timed
+    region): the bulk/dispersion split of K and the RMS relative density
+    difference against the initial state, each timed as a blocking call."""
+    import torch
+    pos0 = torch.from_numpy(p0.copy()).to(pos.device)
+    ctx.kinetic_split(pos, vel, a)          # warm-up
+    ctx.timing(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ks = ctx.kinetic_split(pos, vel, a)
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        rms, cells = ctx.density_rms_diff(pos, pos0)
+    t2 = time.perf_counter()
+    kern = ctx.timing_read()
+    ctx.timing(False)
+    np_ = ctx.np
+    out = {"a": a, "K_disp_over_K": ks["K_disp"] / ks["K"], "rms_rel_diff_vs_initial": rms,
+           "cells": cells, "kinetic_split_ms": (t1 - t0) * 1e3 / reps,
+           "density_rms_diff_ms": (t2 - t1) * 1e3 / reps}
+    for name in ("momentum_deposit", "diag_nodes"):
+        if name in kern:
+            launches, total_ms = kern[name]
+            out[name] = {"launches": launches, "avg_ms": round(total_ms / launches, 5)}
+    if "momentum_deposit" in out:
+        out["momentum_deposit"]["fp64_atomics_per_s"] = 8 * np_ / (
+            out["momentum_deposit"]["avg_ms"] * 1e-3)
     return out
 
 
@@ -262,6 +296,8 @@ def main():
     ap.add_argument("--no-evolved", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-diag", action="store_true",
+                    help="skip the grid diagnostics after the evolved run")
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--no-kernel-pass", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -344,7 +380,8 @@ def main():
                         "(rel-L2 < 1e-5 on rho, phi, Q; tests/test_gpu_parity.py)"}
     if not args.no_evolved:
         re_ = run_gpu(st, n, args.steps, args.warmup, 0.01, kernel_pass=not args.no_kernel_pass,
-                      sort_every=args.sort_every, evolve_to=0.5, box=args.box)
+                      sort_every=args.sort_every, evolve_to=0.5, box=args.box,
+                      diag=not args.no_diag)
         line["evolved"] = {
             "state": f"the same box stepped from a = 0.01 to a = 0.5 "
                      f"({re_['evolve_steps']} steps, untimed), then timed: nonlinear, clustered",
@@ -354,6 +391,8 @@ def main():
         }
         if "kernels" in re_:
             line["evolved"]["kernels"] = kernel_table(re_["kernels"], n, re_["np"], args.steps)
+        if "diag" in re_:
+            line["evolved"]["diagnostics"] = re_["diag"]
     if trace is not None:
         line["serving"] = serve_section(trace, ics)
         del ics

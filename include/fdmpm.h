@@ -32,8 +32,8 @@
  *   particle masses (PM_FIXED32; exactly 2^40 per particle in total) or float
  *   sums of CIC weights (PM_FP32, first 4 N^3 bytes).  Everything else in the
  *   workspace is private.
- * Asynchrony.  All calls except pm_workspace_bytes, pm_energy and pm_destroy
- *   only enqueue work on the context's HIP stream and return.  Argument errors
+ * Asynchrony.  All calls except pm_workspace_bytes, pm_energy,
+ *   pm_kinetic_split, pm_density_rms_diff and pm_destroy only enqueue work on the context's HIP stream and return.  Argument errors
  *   are reported synchronously; a kernel launch error is reported as
  *   PM_EDEVICE.  A context is bound to one stream and is not thread-safe;
  *   distinct contexts on distinct workspaces are independent.
@@ -194,6 +194,39 @@ pm_status pm_sort(pm_ctx* ctx, void* d_pos, float* d_vel, int32_t* d_ids);
  * Leaves the context's delta, phi and Q at d_pos. */
 pm_status pm_energy(pm_ctx* ctx, const void* d_pos, const float* d_vel,
                     double a, pm_energies* out);
+
+/* Grid diagnostics (not part of a step).  Both block until done, use the
+ * workspace's field area as scratch (delta, phi and Q must be recomputed
+ * afterwards, which pm_step, pm_force and pm_energy do by themselves) and
+ * leave the mass mesh of the last state deposited.
+ *
+ * pm_kinetic_split: the kinetic energy K of Eq. (8) (as in pm_energies) split
+ * into the grid-scale bulk motion and the velocity dispersion inside cells
+ * (Sec. II B, Eq. (17)).  The bulk velocity at a mesh node is the mean of
+ * the particle velocities weighted by mass and by the deposit's CIC kernel;
+ * K_bulk = sum over nodes with mass of |P|^2 / (2 M a^2), with M = sum_i m W_i
+ * and P = sum_i m W_i p_i at the node; K_disp = K - K_bulk >= 0 up to
+ * rounding.  Node momenta are FP64 atomic sums, so the last digits of K_bulk
+ * may differ between runs.  a as for pm_energy (1 in a static box). */
+typedef struct {
+  double K;       /* total kinetic energy, sum m p^2 / (2 a^2) */
+  double K_bulk;  /* kinetic energy of the node velocity field */
+  double K_disp;  /* K - K_bulk: velocity dispersion below the mesh scale */
+} pm_kinetic_parts;
+
+pm_status pm_kinetic_split(pm_ctx* ctx, const void* d_pos, const float* d_vel,
+                           double a, pm_kinetic_parts* out);
+
+/* RMS over mesh nodes of the relative density difference
+ * (rho_a - rho_b) / rho_b of two particle states of this context's size and
+ * precision (Sec. III: an FDM run, a, against the CDM run, b, from the same
+ * initial conditions).  Nodes where rho_b is zero are left out; *cells
+ * receives the number of nodes used and *rms is 0 when it is 0.  In the
+ * fixed-point form the numerator is the exact integer mass difference (a
+ * state against itself gives exactly 0); the PM_FP32 deposit sums float
+ * atomics in a varying order, so there it carries rounding of order 1e-7. */
+pm_status pm_density_rms_diff(pm_ctx* ctx, const void* d_pos_a,
+                              const void* d_pos_b, double* rms, int64_t* cells);
 
 /* Per-kernel timing (observability).  While enabled, every kernel the
  * context launches is bracketed by two HIP events recorded on its stream.

@@ -20,9 +20,11 @@ from ._lib import (  # noqa: F401
     pm_batch_step,
     pm_deposit,
     pm_destroy,
+    pm_density_rms_diff,
     pm_energy,
     pm_force,
     pm_init,
+    pm_kinetic_split,
     pm_poisson,
     pm_qpot,
     pm_sort,

@@ -26,7 +26,8 @@ def PM_SORT_EVERY(k: int) -> int:
     return (int(k) & 0xffff) << 8
 
 EXPORTED = ("pm_workspace_bytes", "pm_init", "pm_deposit", "pm_poisson", "pm_qpot",
-            "pm_force", "pm_step", "pm_sort", "pm_energy", "pm_timing_enable", "pm_timing_read",
+            "pm_force", "pm_step", "pm_sort", "pm_energy", "pm_kinetic_split",
+            "pm_density_rms_diff", "pm_timing_enable", "pm_timing_read",
             "pm_batch_workspace_bytes", "pm_batch_init", "pm_batch_slot_offset",
             "pm_batch_set_slot", "pm_batch_step", "pm_batch_destroy", "pm_destroy",
             "pm_strerror")
@@ -53,6 +54,10 @@ class PMParams(ctypes.Structure):
 
 class PMEnergies(ctypes.Structure):
     _fields_ = [("K", c_double), ("W", c_double), ("U", c_double), ("E", c_double)]
+
+
+class PMKineticParts(ctypes.Structure):
+    _fields_ = [("K", c_double), ("K_bulk", c_double), ("K_disp", c_double)]
 
 
 class PMKernelTime(ctypes.Structure):
@@ -92,6 +97,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "pm_step": ([c_void_p, c_void_p, c_void_p, P(c_double), c_int32, c_int32], c_int32),
         "pm_sort": ([c_void_p, c_void_p, c_void_p, c_void_p], c_int32),
         "pm_energy": ([c_void_p, c_void_p, c_void_p, c_double, P(PMEnergies)], c_int32),
+        "pm_kinetic_split": ([c_void_p, c_void_p, c_void_p, c_double, P(PMKineticParts)],
+                             c_int32),
+        "pm_density_rms_diff": ([c_void_p, c_void_p, c_void_p, P(c_double), P(c_int64)], c_int32),
         "pm_timing_enable": ([c_void_p, c_int32], c_int32),
         "pm_timing_read": ([c_void_p, P(PMKernelTime), c_int32, P(c_int32)], c_int32),
         "pm_batch_workspace_bytes": ([P(PMParams), c_int32, P(c_size_t)], c_int32),
@@ -187,6 +195,22 @@ def pm_energy(ctx: int, pos_ptr: int, vel_ptr: int, a: float) -> dict:
     _check(load_library().pm_energy(c_void_p(ctx), c_void_p(pos_ptr), c_void_p(vel_ptr),
                                     float(a), byref(out)), "pm_energy")
     return {"K": out.K, "W": out.W, "U": out.U, "E": out.E}
+
+
+def pm_kinetic_split(ctx: int, pos_ptr: int, vel_ptr: int, a: float) -> dict:
+    out = PMKineticParts()
+    _check(load_library().pm_kinetic_split(c_void_p(ctx), c_void_p(pos_ptr), c_void_p(vel_ptr),
+                                           float(a), byref(out)), "pm_kinetic_split")
+    return {"K": out.K, "K_bulk": out.K_bulk, "K_disp": out.K_disp}
+
+
+def pm_density_rms_diff(ctx: int, pos_a_ptr: int, pos_b_ptr: int) -> tuple:
+    rms = c_double()
+    cells = c_int64()
+    _check(load_library().pm_density_rms_diff(c_void_p(ctx), c_void_p(pos_a_ptr),
+                                              c_void_p(pos_b_ptr), byref(rms), byref(cells)),
+           "pm_density_rms_diff")
+    return rms.value, cells.value
 
 
 def pm_timing_enable(ctx: int, on: bool) -> None:
@@ -290,6 +314,12 @@ class PMContext:
 
     def energy(self, pos, vel, a=1.0):
         return pm_energy(self.ctx, self._pos(pos), self._vec(vel, "vel"), a)
+
+    def kinetic_split(self, pos, vel, a=1.0):
+        return pm_kinetic_split(self.ctx, self._pos(pos), self._vec(vel, "vel"), a)
+
+    def density_rms_diff(self, pos_a, pos_b):
+        return pm_density_rms_diff(self.ctx, self._pos(pos_a), self._pos(pos_b))
 
     def timing(self, on: bool):
         pm_timing_enable(self.ctx, on)

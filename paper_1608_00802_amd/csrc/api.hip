@@ -17,12 +17,13 @@ namespace {
 
 enum KernelClass : int {
   kcFill, kcDeposit, kcR2C, kcFftY, kcFftX, kcFftYInv, kcC2R, kcQpot, kcGatherKD, kcKick,
-  kcForce, kcReduce, kcKinetic, kcSortCount, kcSortScan, kcSortScatter, kcSortCopy, kcCount
+  kcForce, kcReduce, kcKinetic, kcSortCount, kcSortScan, kcSortScatter, kcSortCopy,
+  kcMomentum, kcDiagNodes, kcCount
 };
 const char* const kKernelNames[kcCount] = {
     "fill_zero", "deposit", "r2c_z", "fft_y", "fft_x_green", "fft_y_inv", "c2r_z",
     "qpot", "gather_kick_drift", "kick", "force", "reduce", "kinetic", "sort_count",
-    "sort_scan", "sort_scatter", "sort_copy"};
+    "sort_scan", "sort_scatter", "sort_copy", "momentum_deposit", "diag_nodes"};
 
 struct Timer {
   bool on = false;
@@ -798,6 +799,94 @@ pm_status pm_energy(pm_ctx* c, const void* d_pos, const float* d_vel, double a,
   out->W = 0.5 * host[0] / a;
   out->U = 0.5 * c->hm * c->hm * host[1] / (a * a);
   out->E = out->K + out->W + out->U;
+  return PM_OK;
+}
+
+// After a diagnostic has used delta..spec as FP64 scratch: no field in the
+// workspace is valid any more; a context without quantum pressure keeps Q
+// at zero.
+// Blocks of the node reductions: two partials each fit the workspace's
+// 2 N^3 / kBlock + 1024 partial slots.
+static int diag_node_blocks(const pm_ctx* c) {
+  return diag_blocks((int64_t)c->ncell, 2048);
+}
+
+static pm_status diag_done(pm_ctx* c) {
+  c->have_delta = false;
+  c->have_phi = false;
+  c->have_q = false;
+  c->fields_at_pos = false;
+  if (!c->has_q) PM_TRY(dev(launch_fill_zero(c->q, 4 * c->ncell, c->stream)));
+  return PM_OK;
+}
+
+pm_status pm_kinetic_split(pm_ctx* c, const void* d_pos, const float* d_vel, double a,
+                           pm_kinetic_parts* out) {
+  if (!c || !d_pos || !d_vel || !out) return PM_EINVAL;
+  if (!(a > 0.0) || !isfinite(a)) return PM_EINVAL;
+  if (!c->p.comoving && a != 1.0) return PM_EINVAL;
+  PM_TRY(run_deposit(c, d_pos));
+  // delta and phi are adjacent 4 N^3-byte blocks: one FP64 mesh
+  double* mom = reinterpret_cast<double*>(c->delta);
+  const int nb = diag_node_blocks(c);
+  for (int d = 0; d < 3; ++d) {
+    PM_TRY(timed(c, kcFill, [&] { return launch_fill_zero(mom, 8 * c->ncell, c->stream); }));
+    PM_TRY(timed(c, kcMomentum, [&] {
+      return launch_deposit_momentum(c->fixed, c->logn, d_pos, c->np, d_vel + d * c->np, mom,
+                                     c->sorted ? &c->tmap : nullptr, c->stream);
+    }));
+    PM_TRY(timed(c, kcDiagNodes, [&] {
+      return launch_bulk_nodes(c->fixed, c->mass, mom, (int64_t)c->ncell, c->partials, nb,
+                               c->stream);
+    }));
+    PM_TRY(timed(c, kcReduce, [&] {
+      return launch_reduce(c->partials, nb, 1, c->result + 4 + d, c->stream);
+    }));
+  }
+  double* kp = c->partials + 2 * (size_t)c->q_blocks;
+  PM_TRY(timed(c, kcKinetic, [&] {
+    return launch_kinetic(d_vel, c->np, kp, c->k_blocks, c->stream);
+  }));
+  PM_TRY(timed(c, kcReduce, [&] {
+    return launch_reduce(kp, c->k_blocks, 1, c->result + 3, c->stream);
+  }));
+  double host[4];
+  PM_TRY(dev(hipMemcpyAsync(host, c->result + 3, sizeof(host), hipMemcpyDeviceToHost,
+                            c->stream)));
+  PM_TRY(diag_done(c));
+  PM_TRY(dev(hipStreamSynchronize(c->stream)));
+  const double mp = (double)c->ncell / (double)c->np;
+  out->K = 0.5 * mp * host[0] / (a * a);
+  out->K_bulk = 0.5 * mp * (host[1] + host[2] + host[3]) / (a * a);
+  out->K_disp = out->K - out->K_bulk;
+  return PM_OK;
+}
+
+pm_status pm_density_rms_diff(pm_ctx* c, const void* d_pos_a, const void* d_pos_b,
+                              double* rms, int64_t* cells) {
+  if (!c || !d_pos_a || !d_pos_b || !rms || !cells) return PM_EINVAL;
+  // the reference state's mass mesh is kept in delta..phi (8 N^3 bytes)
+  void* mass_b = c->delta;
+  const size_t mesh_bytes = (c->fixed ? 8 : 4) * c->ncell;
+  PM_TRY(run_deposit(c, d_pos_b));
+  PM_TRY(dev(hipMemcpyAsync(mass_b, c->mass, mesh_bytes, hipMemcpyDeviceToDevice, c->stream)));
+  PM_TRY(run_deposit(c, d_pos_a));
+  const int nb = diag_node_blocks(c);
+  PM_TRY(timed(c, kcDiagNodes, [&] {
+    return launch_rel_diff_nodes(c->fixed, c->mass, mass_b, (int64_t)c->ncell, c->partials, nb,
+                                 c->stream);
+  }));
+  PM_TRY(timed(c, kcReduce, [&] {
+    return launch_reduce(c->partials, nb, 2, c->result + 8, c->stream);
+  }));
+  double host[2];
+  PM_TRY(dev(hipMemcpyAsync(host, c->result + 8, sizeof(host), hipMemcpyDeviceToHost,
+                            c->stream)));
+  PM_TRY(diag_done(c));
+  PM_TRY(dev(hipStreamSynchronize(c->stream)));
+  const int64_t n = (int64_t)host[1];
+  *cells = n;
+  *rms = n > 0 ? sqrt(host[0] / (double)n) : 0.0;
   return PM_OK;
 }
 

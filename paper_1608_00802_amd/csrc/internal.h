@@ -297,4 +297,18 @@ hipError_t launch_kinetic(const float* vel, int64_t np, double* partials, int nb
                           hipStream_t s, const Batch& bt = Batch());
 int kinetic_blocks(int64_t np);
 
+// ---- diag.hip
+// Grid diagnostics: node momenta of one velocity component (FP64 atomics into
+// mom, which the caller zeroes), per-block sums of mom^2 / mass over nodes
+// with mass, and per-block (sum of squared relative differences, node count).
+int diag_blocks(int64_t n, int max_blocks);
+// With tm (sorted context) the tiled form sums each chunk in LDS first.
+hipError_t launch_deposit_momentum(bool fixed, int logn, const void* pos, int64_t np,
+                                   const float* v, double* mom, const TileMap* tm,
+                                   hipStream_t s);
+hipError_t launch_bulk_nodes(bool fixed, const void* mass, const double* mom, int64_t ncell,
+                             double* partials, int nblocks, hipStream_t s);
+hipError_t launch_rel_diff_nodes(bool fixed, const void* mass_a, const void* mass_b,
+                                 int64_t ncell, double* partials, int nblocks, hipStream_t s);
+
 }  // namespace fdm

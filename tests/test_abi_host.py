@@ -48,6 +48,7 @@ def test_struct_layout_matches_header():
     assert _lib.PMParams.four_pi_G_rhobar.offset == 32
     assert _lib.PMParams.rho_fp64_below.offset == 80
     assert ctypes.sizeof(_lib.PMEnergies) == 32
+    assert ctypes.sizeof(_lib.PMKineticParts) == 24
 
 
 def _params(**kw):
@@ -114,6 +115,11 @@ def test_null_context_calls(lib):
     assert lib.pm_force(None, None, None, None, None, 1.0) == _lib.PM_EINVAL
     assert lib.pm_step(None, None, None, ctypes.byref(d), 1, 0) == _lib.PM_EINVAL
     assert lib.pm_energy(None, None, None, 1.0, None) == _lib.PM_EINVAL
+    kp = _lib.PMKineticParts()
+    assert lib.pm_kinetic_split(None, None, None, 1.0, ctypes.byref(kp)) == _lib.PM_EINVAL
+    rms, cells = ctypes.c_double(), ctypes.c_int64()
+    assert lib.pm_density_rms_diff(None, None, None, ctypes.byref(rms),
+                                   ctypes.byref(cells)) == _lib.PM_EINVAL
     assert lib.pm_destroy(None) == _lib.PM_EINVAL
 
 
