@@ -145,9 +145,9 @@ def run_gpu(st, n, steps, warmup, a_start, kernel_pass=True, sort_every=10, fp32
 def diag_pass(ctx, pos, vel, p0, a, reps=3):
     """Grid diagnostics of the state left by the timed steps (after the timed
     region), sorted by tile first so that the momentum deposit takes its
-    tiled path without strays: the bulk/dispersion split of K and the RMS
-    relative density difference against the initial state, each timed as a
-    blocking call."""
+    tiled path without strays: the bulk/dispersion split of K, the RMS
+    relative density difference against the initial state and the power
+    spectrum, each timed as a blocking call."""
     import torch
     pos0 = torch.from_numpy(p0.copy()).to(pos.device)
     ctx.sort(pos, vel)
@@ -160,14 +160,18 @@ def diag_pass(ctx, pos, vel, p0, a, reps=3):
     for _ in range(reps):
         rms, cells = ctx.density_rms_diff(pos, pos0)
     t2 = time.perf_counter()
+    for _ in range(reps):
+        _, pk, _ = ctx.power_spectrum(pos)
+    t3 = time.perf_counter()
     kern = ctx.timing_read()
     ctx.timing(False)
     np_ = ctx.np
     out = {"a": a, "state": "sorted by tile just before", "K_disp_over_K": ks["K_disp"] / ks["K"],
            "rms_rel_diff_vs_initial": rms,
            "cells": cells, "kinetic_split_ms": (t1 - t0) * 1e3 / reps,
-           "density_rms_diff_ms": (t2 - t1) * 1e3 / reps}
-    for name in ("momentum_deposit", "diag_nodes"):
+           "density_rms_diff_ms": (t2 - t1) * 1e3 / reps,
+           "power_spectrum_ms": (t3 - t2) * 1e3 / reps, "power_shells": len(pk)}
+    for name in ("momentum_deposit", "diag_nodes", "fft_x_power"):
         if name in kern:
             launches, total_ms = kern[name]
             out[name] = {"launches": launches, "avg_ms": round(total_ms / launches, 5)}

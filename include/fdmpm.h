@@ -33,7 +33,8 @@
  *   sums of CIC weights (PM_FP32, first 4 N^3 bytes).  Everything else in the
  *   workspace is private.
  * Asynchrony.  All calls except pm_workspace_bytes, pm_energy,
- *   pm_kinetic_split, pm_density_rms_diff and pm_destroy only enqueue work on the context's HIP stream and return.  Argument errors
+ *   pm_kinetic_split, pm_density_rms_diff, pm_power_spectrum and pm_destroy
+ *   only enqueue work on the context's HIP stream and return.  Argument errors
  *   are reported synchronously; a kernel launch error is reported as
  *   PM_EDEVICE.  A context is bound to one stream and is not thread-safe;
  *   distinct contexts on distinct workspaces are independent.
@@ -227,6 +228,21 @@ pm_status pm_kinetic_split(pm_ctx* ctx, const void* d_pos, const float* d_vel,
  * atomics in a varying order, so there it carries rounding of order 1e-7. */
 pm_status pm_density_rms_diff(pm_ctx* ctx, const void* d_pos_a,
                               const void* d_pos_b, double* rms, int64_t* cells);
+
+/* Shell-averaged power spectrum of the density contrast of the state d_pos
+ * (Sec. III measures the FDM suppression as the relative difference of the
+ * FDM and CDM spectra).  delta comes from the CIC deposit (no window
+ * deconvolution), its forward 3-D FFT is unnormalised, and shell b = 1 ..
+ * nbins (nbins <= N/2) holds the modes whose integer mode number |m| lies in
+ * [b - 1/2, b + 1/2).  Host arrays of nbins doubles receive
+ *   k_out[b-1]      = 2 pi b / box (caller's length units),
+ *   p_out[b-1]      = box^3 / N^6 * mean of |delta_m|^2 over the shell,
+ *   counts_out[b-1] = number of modes in the shell (of the full spectrum:
+ *                     the stored half counts modes with 0 < m_z < N/2 twice).
+ * Blocks until done, like the other diagnostics (same scratch use).
+ * PM_EINVAL for null pointers or nbins outside [1, N/2]. */
+pm_status pm_power_spectrum(pm_ctx* ctx, const void* d_pos, int32_t nbins,
+                            double* k_out, double* p_out, double* counts_out);
 
 /* Per-kernel timing (observability).  While enabled, every kernel the
  * context launches is bracketed by two HIP events recorded on its stream.

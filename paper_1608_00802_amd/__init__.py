@@ -26,6 +26,7 @@ from ._lib import (  # noqa: F401
     pm_init,
     pm_kinetic_split,
     pm_poisson,
+    pm_power_spectrum,
     pm_qpot,
     pm_sort,
     pm_step,

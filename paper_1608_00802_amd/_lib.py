@@ -27,7 +27,7 @@ def PM_SORT_EVERY(k: int) -> int:
 
 EXPORTED = ("pm_workspace_bytes", "pm_init", "pm_deposit", "pm_poisson", "pm_qpot",
             "pm_force", "pm_step", "pm_sort", "pm_energy", "pm_kinetic_split",
-            "pm_density_rms_diff", "pm_timing_enable", "pm_timing_read",
+            "pm_density_rms_diff", "pm_power_spectrum", "pm_timing_enable", "pm_timing_read",
             "pm_batch_workspace_bytes", "pm_batch_init", "pm_batch_slot_offset",
             "pm_batch_set_slot", "pm_batch_step", "pm_batch_destroy", "pm_destroy",
             "pm_strerror")
@@ -100,6 +100,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "pm_kinetic_split": ([c_void_p, c_void_p, c_void_p, c_double, P(PMKineticParts)],
                              c_int32),
         "pm_density_rms_diff": ([c_void_p, c_void_p, c_void_p, P(c_double), P(c_int64)], c_int32),
+        "pm_power_spectrum": ([c_void_p, c_void_p, c_int32, P(c_double), P(c_double),
+                               P(c_double)], c_int32),
         "pm_timing_enable": ([c_void_p, c_int32], c_int32),
         "pm_timing_read": ([c_void_p, P(PMKernelTime), c_int32, P(c_int32)], c_int32),
         "pm_batch_workspace_bytes": ([P(PMParams), c_int32, P(c_size_t)], c_int32),
@@ -213,6 +215,17 @@ def pm_density_rms_diff(ctx: int, pos_a_ptr: int, pos_b_ptr: int) -> tuple:
     return rms.value, cells.value
 
 
+def pm_power_spectrum(ctx: int, pos_ptr: int, nbins: int) -> tuple:
+    """(k, P, counts) as three lists of nbins floats."""
+    nb = int(nbins)
+    k = (c_double * max(nb, 1))()
+    p = (c_double * max(nb, 1))()
+    cnt = (c_double * max(nb, 1))()
+    _check(load_library().pm_power_spectrum(c_void_p(ctx), c_void_p(pos_ptr), nb, k, p, cnt),
+           "pm_power_spectrum")
+    return list(k)[:nb], list(p)[:nb], list(cnt)[:nb]
+
+
 def pm_timing_enable(ctx: int, on: bool) -> None:
     _check(load_library().pm_timing_enable(c_void_p(ctx), int(bool(on))), "pm_timing_enable")
 
@@ -320,6 +333,9 @@ class PMContext:
 
     def density_rms_diff(self, pos_a, pos_b):
         return pm_density_rms_diff(self.ctx, self._pos(pos_a), self._pos(pos_b))
+
+    def power_spectrum(self, pos, nbins=None):
+        return pm_power_spectrum(self.ctx, self._pos(pos), self.n // 2 if nbins is None else nbins)
 
     def timing(self, on: bool):
         pm_timing_enable(self.ctx, on)

@@ -18,12 +18,12 @@ namespace {
 enum KernelClass : int {
   kcFill, kcDeposit, kcR2C, kcFftY, kcFftX, kcFftYInv, kcC2R, kcQpot, kcGatherKD, kcKick,
   kcForce, kcReduce, kcKinetic, kcSortCount, kcSortScan, kcSortScatter, kcSortCopy,
-  kcMomentum, kcDiagNodes, kcCount
+  kcMomentum, kcDiagNodes, kcPower, kcCount
 };
 const char* const kKernelNames[kcCount] = {
     "fill_zero", "deposit", "r2c_z", "fft_y", "fft_x_green", "fft_y_inv", "c2r_z",
     "qpot", "gather_kick_drift", "kick", "force", "reduce", "kinetic", "sort_count",
-    "sort_scan", "sort_scatter", "sort_copy", "momentum_deposit", "diag_nodes"};
+    "sort_scan", "sort_scatter", "sort_copy", "momentum_deposit", "diag_nodes", "fft_x_power"};
 
 struct Timer {
   bool on = false;
@@ -887,6 +887,38 @@ pm_status pm_density_rms_diff(pm_ctx* c, const void* d_pos_a, const void* d_pos_
   const int64_t n = (int64_t)host[1];
   *cells = n;
   *rms = n > 0 ? sqrt(host[0] / (double)n) : 0.0;
+  return PM_OK;
+}
+
+pm_status pm_power_spectrum(pm_ctx* c, const void* d_pos, int32_t nbins, double* k_out,
+                            double* p_out, double* counts_out) {
+  if (!c || !d_pos || !k_out || !p_out || !counts_out) return PM_EINVAL;
+  if (nbins < 1 || nbins > c->N / 2) return PM_EINVAL;
+  PM_TRY(run_deposit(c, d_pos));
+  PM_TRY(timed(c, kcR2C, [&] {
+    return launch_r2c_z(c->logn, c->fixed ? kSrcMass64 : kSrcAcc32, c->mass, c->delta, c->spec,
+                        c->tw, c->conv, c->stream);
+  }));
+  PM_TRY(timed(c, kcFftY, [&] { return launch_fft_y(c->logn, c->spec, c->tw, false, c->stream); }));
+  // per-block shell sums in the phi block (4 N^3 bytes hold them for every N)
+  double* blk = reinterpret_cast<double*>(c->phi);
+  PM_TRY(timed(c, kcPower, [&] {
+    return launch_fft_x_power(c->logn, c->spec, c->tw, nbins, blk, c->partials, c->stream);
+  }));
+  std::vector<double> host(2 * (size_t)(nbins + 1));
+  PM_TRY(dev(hipMemcpyAsync(host.data(), c->partials, host.size() * sizeof(double),
+                            hipMemcpyDeviceToHost, c->stream)));
+  PM_TRY(diag_done(c));
+  PM_TRY(dev(hipStreamSynchronize(c->stream)));
+  const double nn = (double)c->N;
+  const double box = c->p.box;
+  const double scale = box * box * box / (nn * nn * nn * nn * nn * nn);
+  for (int b = 1; b <= nbins; ++b) {
+    const double w = host[2 * b + 1];
+    k_out[b - 1] = 2.0 * M_PI * b / box;
+    p_out[b - 1] = w > 0.0 ? host[2 * b] / w * scale : 0.0;
+    counts_out[b - 1] = w;
+  }
   return PM_OK;
 }
 

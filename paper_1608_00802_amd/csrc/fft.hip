@@ -568,6 +568,107 @@ hipError_t launch_fft_y(int logn, float2* spec, const float2* tw, bool inverse,
   return hipGetLastError();
 }
 
+// Power spectrum pass: the forward x transform of the x pass, then |X|^2 of
+// every mode binned by its integer mode number |m| into shells
+// [b - 1/2, b + 1/2), b = 1..nb, in FP64 LDS bins; each block writes its nb
+// (sum, weight) pairs to partials[block][2 (nb + 1)] with plain stores.  The
+// spectrum holds kz = 0..N/2 only: modes with 0 < kz < N/2 stand for their
+// conjugates too (weight 2).
+template <int LOGN>
+__global__ void __launch_bounds__(RegTiles<1 << LOGN>::XT) k_fft_x_power_reg(
+    const float2* __restrict__ spec, const float2* __restrict__ tw, int nb,
+    double* __restrict__ partials) {
+  constexpr int N = 1 << LOGN;
+  constexpr int R1 = Split<N>::R1, R2 = Split<N>::R2;
+  constexpr int TC = RegTiles<N>::TC;
+  constexpr int XT = RegTiles<N>::XT;
+  constexpr int XF = R2 * (R1 + 1);
+  constexpr int NA = TC * R2, NB = TC * R1;
+  constexpr int PA = (NA + XT - 1) / XT, PB = (NB + XT - 1) / XT;
+  __shared__ float2 ex[TC * XF];
+  __shared__ float2 tws[N];
+  __shared__ double bins[2 * (N / 2 + 1)];
+  const int tid = threadIdx.x;
+  const int b = (int)blockIdx.x;
+  const int kz = b / (N / TC);
+  const int y0 = (b % (N / TC)) * TC;
+  auto at = [&](int x, int c) -> float2 { return spec[((size_t)kz * N + x) * N + y0 + c]; };
+  float2 v[PA][R1];
+#pragma unroll
+  for (int p = 0; p < PA; ++p) {
+    const int it = tid + p * XT;
+    if (NA % XT == 0 || it < NA) {
+      const int c = it % TC, n2 = it / TC;
+#pragma unroll
+      for (int n1 = 0; n1 < R1; ++n1) v[p][n1] = at(R2 * n1 + n2, c);
+    }
+  }
+  for (int k = tid; k < N; k += XT) tws[k] = tw[k];
+  for (int k = tid; k < 2 * (N / 2 + 1); k += XT) bins[k] = 0.0;
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < PA; ++p) {
+    const int it = tid + p * XT;
+    if (NA % XT == 0 || it < NA) {
+      const int c = it % TC, n2 = it / TC;
+      fft_first<N, R1, false>(v[p], n2, tws);
+#pragma unroll
+      for (int k1 = 0; k1 < R1; ++k1) ex[c * XF + n2 * (R1 + 1) + k1] = v[p][k1];
+    }
+  }
+  __syncthreads();
+  const double wz = (kz == 0 || kz == N / 2) ? 1.0 : 2.0;
+#pragma unroll
+  for (int p = 0; p < PB; ++p) {
+    const int it = tid + p * XT;
+    if (NB % XT == 0 || it < NB) {
+      const int c = it % TC, k1 = it / TC;
+      float2 u[R2];
+#pragma unroll
+      for (int n2 = 0; n2 < R2; ++n2) u[n2] = ex[c * XF + n2 * (R1 + 1) + k1];
+      dft_reg<R2, false, N / R2>(u, tws);
+      const int ky = y0 + c;
+      const int my = ky <= N / 2 ? ky : ky - N;
+      const int myz = my * my + kz * kz;
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) {
+        const int kx = k1 + R1 * k2;
+        const int mx = kx <= N / 2 ? kx : kx - N;
+        const int m2 = mx * mx + myz;
+        // shell index: the integer bin with (2 bin - 1)^2 <= 4 m2 < (2 bin + 1)^2
+        int bin = (int)(sqrtf((float)m2) + 0.5f);
+        if ((2 * bin + 1) * (2 * bin + 1) <= 4 * m2) ++bin;
+        if (bin > 0 && (2 * bin - 1) * (2 * bin - 1) > 4 * m2) --bin;
+        if (bin >= 1 && bin <= nb) {
+          const double re = (double)u[k2].x, im = (double)u[k2].y;
+          atomicAdd(&bins[2 * bin], wz * (re * re + im * im));
+          atomicAdd(&bins[2 * bin + 1], wz);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  double* out = partials + (size_t)b * 2 * (nb + 1);
+  for (int k = tid; k < 2 * (nb + 1); k += XT) out[k] = bins[k];
+}
+
+// out[j] = sum over blocks of partials[block][j], j < ncomp: one block per j.
+__global__ void __launch_bounds__(kBlock) k_sum_columns(const double* __restrict__ partials,
+                                                        int nblocks, int ncomp,
+                                                        double* __restrict__ out) {
+  __shared__ double red[kBlock];
+  const int j = blockIdx.x;
+  double t = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += kBlock) t += partials[(size_t)b * ncomp + j];
+  red[threadIdx.x] = t;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[j] = red[0];
+}
+
 hipError_t launch_fft_x_green(int logn, float2* spec, const float2* tw, const float* s2,
                               float green_scale, hipStream_t s, const Batch& bt) {
 #define L_(LN)                                                                      \
@@ -579,6 +680,34 @@ hipError_t launch_fft_x_green(int logn, float2* spec, const float2* tw, const fl
   }
   FDM_LOGN_SWITCH(logn, L_)
 #undef L_
+  return hipGetLastError();
+}
+
+int power_blocks(int logn) {
+  switch (logn) {
+#define B_(LN) \
+    case LN: return ((1 << LN) / 2 + 1) * ((1 << LN) / RegTiles<(1 << LN)>::TC);
+    B_(4) B_(5) B_(6) B_(7) B_(8) B_(9)
+#undef B_
+    default: return 0;
+  }
+}
+
+hipError_t launch_fft_x_power(int logn, const float2* spec, const float2* tw, int nb,
+                              double* partials, double* out, hipStream_t s) {
+  if (nb < 1 || nb > (1 << logn) / 2) return hipErrorInvalidValue;
+#define L_(LN)                                                                      \
+  {                                                                                 \
+    constexpr int N_ = 1 << LN;                                                     \
+    dim3 g((N_ / 2 + 1) * (N_ / RegTiles<N_>::TC));                                 \
+    hipLaunchKernelGGL((k_fft_x_power_reg<LN>), g, dim3(RegTiles<N_>::XT), 0, s, spec, tw, nb, \
+                       partials);                                                   \
+  }
+  FDM_LOGN_SWITCH(logn, L_)
+#undef L_
+  const int ncomp = 2 * (nb + 1);
+  hipLaunchKernelGGL(k_sum_columns, dim3(ncomp), dim3(kBlock), 0, s, partials,
+                     power_blocks(logn), ncomp, out);
   return hipGetLastError();
 }
 

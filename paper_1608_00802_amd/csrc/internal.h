@@ -297,6 +297,14 @@ hipError_t launch_kinetic(const float* vel, int64_t np, double* partials, int nb
                           hipStream_t s, const Batch& bt = Batch());
 int kinetic_blocks(int64_t np);
 
+// ---- fft.hip, power spectrum: the forward x transform of a spectrum after
+// r2c_z and the forward y pass, |X|^2 binned into shells b = 1..nb of integer
+// mode number; per-block bins go to partials (power_blocks(logn) x 2 (nb + 1)
+// doubles), their sums to out[2 b] (power) and out[2 b + 1] (mode weight).
+int power_blocks(int logn);
+hipError_t launch_fft_x_power(int logn, const float2* spec, const float2* tw, int nb,
+                              double* partials, double* out, hipStream_t s);
+
 // ---- diag.hip
 // Grid diagnostics: node momenta of one velocity component (FP64 atomics into
 // mom, which the caller zeroes), per-block sums of mom^2 / mass over nodes

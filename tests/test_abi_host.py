@@ -120,6 +120,8 @@ def test_null_context_calls(lib):
     rms, cells = ctypes.c_double(), ctypes.c_int64()
     assert lib.pm_density_rms_diff(None, None, None, ctypes.byref(rms),
                                    ctypes.byref(cells)) == _lib.PM_EINVAL
+    arr = (ctypes.c_double * 4)()
+    assert lib.pm_power_spectrum(None, None, 4, arr, arr, arr) == _lib.PM_EINVAL
     assert lib.pm_destroy(None) == _lib.PM_EINVAL
 
 

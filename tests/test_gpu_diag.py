@@ -236,3 +236,78 @@ def test_steps_after_diagnostics_are_unchanged(pm, gpu, m_ev):
     torch.cuda.synchronize()
     assert torch.equal(p1, p2)
     assert torch.equal(v1, v2)
+
+
+# ------------------------------------------------------------ power spectrum
+
+def _oracle_power(pos_t, n, op, fp32, nbins=None):
+    x = positions_cells(pos_t, n, fp32)
+    delta = oracle.deposit(x, op) - 1.0
+    return oracle.power_spectrum(delta, op.box, nbins)
+
+
+def _check_power(got, ref, tol):
+    # relative tolerance per shell, with a floor at 1e-9 of the largest shell
+    # for the float FFT's rounding where the spectrum has fallen far below it
+    k, p, c = (np.asarray(a) for a in got)
+    rk, rp, rc = ref
+    assert np.array_equal(c, rc)
+    assert np.allclose(k, rk, rtol=1e-14, atol=0)
+    err = np.abs(p - rp)
+    assert np.all(err <= tol * rp + 1e-9 * rp.max()), np.max(err / rp)
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+@pytest.mark.parametrize("n", [16, 32, 64])
+def test_power_spectrum_vs_oracle(pm, gpu, precision, n):
+    # CDM initial conditions (no FDM cutoff): power in every shell
+    st = zeldovich_state(n, 2.0, 0.1, seed=13, m_ev=None)
+    lp, op = cosmo_setup(n, 2.0, 2.5e-22, precision=precision)
+    fp32 = precision == 0
+    ctx = pm.PMContext(lp, device=gpu)
+    pos, _ = to_device(st, gpu, fp32_positions=fp32)
+    got = ctx.power_spectrum(pos)
+    _check_power(got, _oracle_power(pos, n, op, fp32), 2e-5 if precision == 1 else 2e-4)
+    # fewer bins: the same leading shells (a new deposit: in FP32 its float
+    # atomics add in another order)
+    got5 = ctx.power_spectrum(pos, 5)
+    assert got5[2] == got[2][:5]
+    assert np.allclose(got5[1], got[1][:5], rtol=1e-12 if precision == 1 else 1e-6)
+
+
+def test_power_spectrum_single_mode_along_z(pm, gpu):
+    # a lattice displaced along z by one sine mode: its power sits in shell
+    # `mode` at m_z = +-mode (stored once, counted for its conjugate)
+    from synth import sine_mode_state
+    n = 32
+    st = sine_mode_state(n, mode=3, amp_cells=1e-2, axis=2)
+    lp, op = cosmo_setup(n, 2.0, 2.5e-22)
+    ctx = pm.PMContext(lp, device=gpu)
+    pos, _ = to_device(st, gpu)
+    k, p, c = ctx.power_spectrum(pos)
+    rk, rp, rc = _oracle_power(pos, n, op, False)
+    assert np.array_equal(np.asarray(c), rc)
+    assert abs(p[2] - rp[2]) <= 1e-5 * rp[2]
+    assert p[2] > 1e6 * max(p[b] for b in range(len(p)) if b != 2)
+
+
+def test_power_spectrum_full_size(pm, gpu):
+    # 256^3 particles on a 256^3 mesh (the benchmark box), every shell
+    n = 256
+    st = zeldovich_state(n, 10.0, 0.05, seed=1, m_ev=None)
+    lp, op = cosmo_setup(n, 10.0, 1e-22)
+    ctx = pm.PMContext(lp, device=gpu)
+    pos, _ = to_device(st, gpu)
+    got = ctx.power_spectrum(pos)
+    _check_power(got, _oracle_power(pos, n, op, False), 2e-5)
+
+
+def test_power_spectrum_rejects_bad_bins(pm, gpu):
+    n = 16
+    lp, _ = cosmo_setup(n, 2.0, 2.5e-22)
+    ctx = pm.PMContext(lp, device=gpu)
+    st = zeldovich_state(n, 2.0, 0.1, seed=1, m_ev=2.5e-22)
+    pos, _ = to_device(st, gpu)
+    for nb in (0, n // 2 + 1):
+        with pytest.raises(pm.PMError):
+            ctx.power_spectrum(pos, nb)

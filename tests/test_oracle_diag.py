@@ -180,3 +180,43 @@ def test_d9_empty_reference_nodes_are_left_out():
     rel[: n ** 3 // 8] = 7.0
     assert math.isclose(rms2, math.sqrt(float(np.mean(rel * rel))), rel_tol=1e-12)
 
+
+
+# ------------------------------------------------------------ power spectrum
+
+def test_d10_power_of_a_z_cosine_counts_its_conjugate():
+    # a cosine along z lives at m_z = +-3; the stored half spectrum holds only
+    # m_z = 3, which must count twice, giving the same total as along x
+    n, box, amp = 16, 5.0, 0.1
+    z = np.arange(n)
+    delta = amp * np.cos(2 * np.pi * 3 * z / n)[None, None, :] * np.ones((n, n, 1))
+    k, pk, cnt = oracle.power_spectrum(delta, box)
+    expect_total = 2 * (amp * n ** 3 / 2) ** 2 * box ** 3 / n ** 6
+    assert abs(pk[2] * cnt[2] - expect_total) < 1e-12 * expect_total
+    assert np.all(pk[np.arange(len(pk)) != 2] < 1e-25)
+    assert np.allclose(k, 2 * np.pi * np.arange(1, n // 2 + 1) / box)
+
+
+def test_d11_shell_counts_by_enumeration():
+    # every integer vector of the full n^3 spectrum with |m| in [b - 1/2,
+    # b + 1/2) is counted once, whichever half stores it
+    n = 12
+    delta = np.random.default_rng(0).standard_normal((n, n, n))
+    _, _, cnt = oracle.power_spectrum(delta, 1.0)
+    m = np.fft.fftfreq(n, 1.0 / n)
+    mx, my, mz = np.meshgrid(m, m, m, indexing="ij")
+    mag = np.sqrt(mx ** 2 + my ** 2 + mz ** 2).ravel()
+    for b in range(1, n // 2 + 1):
+        assert cnt[b - 1] == np.count_nonzero((mag >= b - 0.5) & (mag < b + 0.5))
+
+
+def test_d12_power_of_white_noise_is_its_variance():
+    # Parseval: for white noise the mean |delta_m|^2 over all modes is
+    # n^3 var, so every shell's P is near var * box^3 / n^3
+    n, box = 32, 7.0
+    rng = np.random.default_rng(1)
+    delta = rng.standard_normal((n, n, n)) * 0.3
+    _, pk, cnt = oracle.power_spectrum(delta, box)
+    expect = 0.09 * box ** 3 / n ** 3
+    big = cnt > 500
+    assert np.all(np.abs(pk[big] / expect - 1) < 0.15)
