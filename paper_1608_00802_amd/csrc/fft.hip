@@ -589,7 +589,9 @@ __global__ void __launch_bounds__(RegTiles<1 << LOGN>::XT) k_fft_x_power_reg(
   __shared__ float2 tws[N];
   __shared__ double bins[2 * (N / 2 + 1)];
   const int tid = threadIdx.x;
-  const int b = (int)blockIdx.x;
+  // the blocks that share a 128-byte line of a column run on one XCD, as in
+  // the Poisson x pass (one L2 fetch of each line instead of one per block)
+  const int b = (int)xcd_block(blockIdx.x, gridDim.x, RegTiles<N>::XG);
   const int kz = b / (N / TC);
   const int y0 = (b % (N / TC)) * TC;
   auto at = [&](int x, int c) -> float2 { return spec[((size_t)kz * N + x) * N + y0 + c]; };
