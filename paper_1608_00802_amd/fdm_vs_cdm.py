@@ -1,7 +1,8 @@
-"""FDM against CDM from identical initial conditions (Sec. III, first test).
+"""FDM against CDM from identical initial conditions (Sec. III).
 
-Zel'dovich initial conditions with the CDM transfer function at z = 100 are
-evolved twice to z = 18.5: once with quantum pressure (boson mass m, comoving
+Zel'dovich initial conditions at z = 100 (first test: CDM transfer function,
+to z = 18.5; second test: the FDM transfer function of the boson mass, to
+z = 2.38) are evolved twice: once with quantum pressure (boson mass m, comoving
 Q of Eq. (18)) and once without (hbar/m = 0), on one step schedule.  The
 power spectra of both runs are then compared shell by shell, (P_FDM -
 P_CDM) / P_CDM, beside the quantum Jeans wavenumber k_J(a) of Eq. (20) at the
@@ -21,6 +22,7 @@ Units follow the library's comoving convention: lengths in Mpc/h, time in
 h = 0.7; its cosmology is Omega_m = 0.25, Omega_Lambda = 0.75.
 
     python -m paper_1608_00802_amd.fdm_vs_cdm --n 256
+    python -m paper_1608_00802_amd.fdm_vs_cdm --ics fdm --box 7.0 --z-end 2.38 --n 256
 """
 
 from __future__ import annotations
@@ -73,14 +75,20 @@ def plan_chunk(a: float, count: int, hm_cells: float, vmax: float, omega_m: floa
 def run(n: int = 256, box: float = 1.4, m_ev: float = 2.5e-22, seed: int = 1,
         omega_m: float = 0.25, h: float = 0.7, a_start: float = A_START, a_end: float = A_END,
         chunk: int = 10, device=None, keep_states: bool = False, max_steps: int = 4000,
-        progress=None) -> dict:
+        progress=None, ics: str = "cdm") -> dict:
+    """ics = "cdm": initial power with the CDM transfer function (the first
+    test); "fdm": with the FDM transfer function of the same boson mass
+    (the second test, Fig. 6), both runs still starting from one state."""
     import torch
 
     import paper_1608_00802_amd as pm
     from synth import zeldovich_state
 
     dev = device if device is not None else torch.device("cuda:0")
-    st = zeldovich_state(n, box, a_start, seed, m_ev=None, om=omega_m, h=h)
+    if ics not in ("cdm", "fdm"):
+        raise ValueError("ics: 'cdm' or 'fdm'")
+    st = zeldovich_state(n, box, a_start, seed, m_ev=m_ev if ics == "fdm" else None, om=omega_m,
+                         h=h)
     hm = hbar_over_m(m_ev, h)
     hm_cells = hm / (box / n) ** 2
 
@@ -119,6 +127,7 @@ def run(n: int = 256, box: float = 1.4, m_ev: float = 2.5e-22, seed: int = 1,
     p_f, p_c, p_start = np.asarray(p_f), np.asarray(p_c), np.asarray(p_start)
     out = {
         "n": n, "box_mpch": box, "m_ev": m_ev, "hbar_over_m": hm, "omega_m": omega_m,
+        "ics": ics,
         "seed": seed, "a_start": a_start, "a_end": times[-1], "steps": len(times) - 1,
         "reached_a_end": times[-1] >= a_end,
         "wall_s": wall, "finite": bool(torch.isfinite(vel_f).all().item()
@@ -136,15 +145,19 @@ def run(n: int = 256, box: float = 1.4, m_ev: float = 2.5e-22, seed: int = 1,
 
 
 def summary(res: dict) -> dict:
-    """Mean relative difference well below k_J(start), between the two Jeans
-    scales, and above k_J(end)."""
+    """Largest and smallest relative difference with their k; mean relative
+    difference well below k_J(start), between the two Jeans scales, and
+    above twice k_J(end)."""
     k = np.asarray(res["k"])
     rd = np.asarray(res["rel_diff"])
     lo = k < 0.5 * res["k_J_start"]
     mid = (k >= res["k_J_start"]) & (k <= res["k_J_end"])
     hi = k > 2.0 * res["k_J_end"]
     pick = lambda m: float(rd[m].mean()) if m.any() else None  # noqa: E731
-    return {"below_half_kJ_start": pick(lo), "between_kJ": pick(mid),
+    top = int(np.argmax(rd))
+    return {"max_rel_diff": float(rd[top]), "k_at_max": float(k[top]),
+            "min_rel_diff": float(rd.min()), "k_at_min": float(k[int(np.argmin(rd))]),
+            "below_half_kJ_start": pick(lo), "between_kJ": pick(mid),
             "above_2kJ_end": pick(hi),
             "growth_cdm_above_2kJ_end": float(np.mean(np.asarray(res["P_cdm"])[hi] /
                                                       np.asarray(res["P_start"])[hi]))
@@ -160,10 +173,14 @@ def main(argv=None):
     ap.add_argument("--box", type=float, default=1.4, help="box side in Mpc/h")
     ap.add_argument("--m-ev", type=float, default=2.5e-22)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--ics", choices=("cdm", "fdm"), default="cdm",
+                    help="transfer function of the initial power (first or second test)")
+    ap.add_argument("--z-end", type=float, default=1.0 / A_END - 1.0)
     ap.add_argument("--max-steps", type=int, default=4000,
                     help="stop there (the velocity bound shortens the steps of a run gone unstable)")
     args = ap.parse_args(argv)
-    res = run(args.n, args.box, args.m_ev, args.seed, max_steps=args.max_steps,
+    res = run(args.n, args.box, args.m_ev, args.seed, a_end=1.0 / (1.0 + args.z_end),
+              max_steps=args.max_steps, ics=args.ics,
               progress=lambda msg: print(msg, file=sys.stderr, flush=True))
     res.pop("times")
     res["summary"] = summary(res)
