@@ -35,4 +35,9 @@ from .pm import (  # noqa: F401
     omega_max,
     timestep,
     power_spectrum,
+    spline_w,
+    spline_dw,
+    spline_deposit,
+    spline_qforce,
+    spline_kinetic_rho,
 )

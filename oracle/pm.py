@@ -12,6 +12,8 @@ order of the displayed equations in the paper:
   Eq. (8)  discrete K_v = sum_i m_i qdot_i^2 / 2
   Eq. (9)  density from particles with an assignment kernel W
   Eq. (11) discrete K_rho with central differences on the mesh
+  Eq. (14) equation of motion: quantum force by the kernel gradient
+  Eq. (15) cubic spline smoothing kernel
   Eq. (16) scale symmetry                                     (Sec. II B)
   Eq. (17) bulk velocity field of the particles on the mesh   (Sec. II B)
   Eq. (18) comoving Q carries an extra 1/a^2                  (Sec. III)
@@ -460,3 +462,88 @@ def density_rms_diff(pos_a, pos_b, p: Params):
         return 0.0, 0
     rel = (ra[keep] - rb[keep]) / rb[keep]
     return math.sqrt(float(np.mean(rel * rel))), cnt
+
+
+# ---------------------------------------------------------------- spline kernel (the paper's own)
+
+def spline_w(r, h):
+    """Eq. (15): the cubic spline smoothing kernel of support h,
+    W = 8/(pi h^3) [1 - 6 q^2 + 6 q^3] for q = r/h <= 1/2, 8/(pi h^3) 2 (1 - q)^3
+    for 1/2 < q <= 1, zero beyond."""
+    q = np.asarray(r, dtype=np.float64) / h
+    c = 8.0 / (math.pi * h ** 3)
+    inner = 1.0 - 6.0 * q ** 2 + 6.0 * q ** 3
+    outer = 2.0 * (1.0 - q) ** 3
+    return c * np.where(q <= 0.5, inner, np.where(q <= 1.0, outer, 0.0))
+
+
+def spline_dw(r, h):
+    """dW/dr of Eq. (15)."""
+    q = np.asarray(r, dtype=np.float64) / h
+    c = 8.0 / (math.pi * h ** 3) / h
+    inner = -12.0 * q + 18.0 * q ** 2
+    outer = -6.0 * (1.0 - q) ** 2
+    return c * np.where(q <= 0.5, inner, np.where(q <= 1.0, outer, 0.0))
+
+
+def _spline_offsets(h_cells):
+    m = int(math.ceil(h_cells)) + 1
+    return range(-m, m + 1)
+
+
+def spline_deposit(pos, p: Params, h: float) -> np.ndarray:
+    """rho/rho_bar on the mesh nodes from Eq. (9) with the kernel of Eq. (15):
+    rho(x_j) = sum_i m W(|x_j - q_i|, h), m = box^3/Np.  Every node within h of
+    a particle is visited (a cube of offsets around its cell)."""
+    n = p.n
+    npart = pos.shape[0]
+    dx = p.dx
+    u = np.asarray(pos, dtype=np.float64) / dx
+    base = np.floor(u).astype(np.int64)
+    rho = np.zeros(n ** 3)
+    mp = p.box ** 3 / npart
+    offs = list(_spline_offsets(h / dx))
+    for ox in offs:
+        for oy in offs:
+            for oz in offs:
+                node = base + np.array([ox, oy, oz])
+                r = np.sqrt(np.sum(((node - u) * dx) ** 2, axis=1))
+                w = spline_w(r, h)
+                idx = ((node[:, 0] % n) * n + node[:, 1] % n) * n + node[:, 2] % n
+                rho += np.bincount(idx, weights=mp * w, minlength=n ** 3)
+    return rho.reshape(n, n, n)          # mean density is one: rho/rho_bar
+
+
+def spline_qforce(pos, q, p: Params, h: float) -> np.ndarray:
+    """Acceleration from the quantum potential on the nodes by the kernel
+    gradient, Eq. (14): a_i = dx^3 sum_j Q_j grad W(x_j - q_i), the sign taken
+    so that a = -grad Q (reading R3); it is minus the q_i-derivative of the
+    mesh energy whose node variation is Q (see spline_kinetic_rho)."""
+    n = p.n
+    dx = p.dx
+    u = np.asarray(pos, dtype=np.float64) / dx
+    base = np.floor(u).astype(np.int64)
+    qf = np.asarray(q, dtype=np.float64).ravel()
+    acc = np.zeros((pos.shape[0], 3))
+    offs = list(_spline_offsets(h / dx))
+    for ox in offs:
+        for oy in offs:
+            for oz in offs:
+                node = base + np.array([ox, oy, oz])
+                d = (node - u) * dx
+                r = np.sqrt(np.sum(d ** 2, axis=1))
+                g = np.where(r > 0.0, spline_dw(r, h) / np.where(r > 0.0, r, 1.0), 0.0)
+                idx = ((node[:, 0] % n) * n + node[:, 1] % n) * n + node[:, 2] % n
+                acc += (qf[idx] * g)[:, None] * d
+    return acc * dx ** 3
+
+
+def spline_kinetic_rho(pos, p: Params, h: float) -> float:
+    """K_rho of Eq. (12) on the spline density per unit mass density
+    (rho in units of the mean), with forward differences, the exact
+    conjugate of the 7-point Laplacian in Q; no floor (rho > 0 assumed)."""
+    s = np.sqrt(spline_deposit(pos, p, h))
+    tot = 0.0
+    for ax in range(3):
+        tot += float(np.sum((np.roll(s, -1, axis=ax) - s) ** 2))
+    return p.hbar_m ** 2 / 2.0 * p.dx * tot
