@@ -244,6 +244,28 @@ pm_status pm_density_rms_diff(pm_ctx* ctx, const void* d_pos_a,
 pm_status pm_power_spectrum(pm_ctx* ctx, const void* d_pos, int32_t nbins,
                             double* k_out, double* p_out, double* counts_out);
 
+/* The paper's own coupling of particles and mesh (Sec. II A), as two
+ * composable steps (the step loop of pm_step keeps cloud-in-cell):
+ *
+ * pm_spline_density: d_delta (float [N^3], caller-owned) receives
+ * rho/rho_bar - 1 at the mesh nodes from Eq. (9) with the cubic spline of
+ * Eq. (15), smoothing length h in cells (the paper uses 3.5 to 4):
+ * rho(x_j) = sum_i m W(|x_j - q_i|, h), m = N^3 / Np mean densities.  FP32
+ * atomic sums (last bits vary from run to run).  Pass the result to pm_qpot
+ * for Q on the nodes.
+ *
+ * pm_spline_qforce: d_acc ([3][Np] float) receives the quantum acceleration of
+ * every particle by the kernel gradient, Eq. (14): a_i = sum_j Q_j
+ * grad W(x_j - q_i) (cell units, dx = 1), with the sign that makes it
+ * -grad Q, i.e. minus the particle derivative of the discrete K_rho of
+ * Eq. (12) whose node derivative is Q.  d_q is float [N^3] as from pm_qpot.
+ *
+ * Both enqueue only.  PM_EINVAL for null pointers or h outside
+ * [0.5, 16] or so wide that 2 floor(h) + 2 > N. */
+pm_status pm_spline_density(pm_ctx* ctx, const void* d_pos, double h, float* d_delta);
+pm_status pm_spline_qforce(pm_ctx* ctx, const void* d_pos, const float* d_q, double h,
+                           float* d_acc);
+
 /* Per-kernel timing (observability).  While enabled, every kernel the
  * context launches is bracketed by two HIP events recorded on its stream.
  * pm_timing_enable(ctx, 1) clears the counters and starts recording;

@@ -29,6 +29,8 @@ from ._lib import (  # noqa: F401
     pm_power_spectrum,
     pm_qpot,
     pm_sort,
+    pm_spline_density,
+    pm_spline_qforce,
     pm_step,
     pm_timing_enable,
     pm_timing_read,

@@ -27,7 +27,8 @@ def PM_SORT_EVERY(k: int) -> int:
 
 EXPORTED = ("pm_workspace_bytes", "pm_init", "pm_deposit", "pm_poisson", "pm_qpot",
             "pm_force", "pm_step", "pm_sort", "pm_energy", "pm_kinetic_split",
-            "pm_density_rms_diff", "pm_power_spectrum", "pm_timing_enable", "pm_timing_read",
+            "pm_density_rms_diff", "pm_power_spectrum", "pm_spline_density",
+            "pm_spline_qforce", "pm_timing_enable", "pm_timing_read",
             "pm_batch_workspace_bytes", "pm_batch_init", "pm_batch_slot_offset",
             "pm_batch_set_slot", "pm_batch_step", "pm_batch_destroy", "pm_destroy",
             "pm_strerror")
@@ -102,6 +103,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "pm_density_rms_diff": ([c_void_p, c_void_p, c_void_p, P(c_double), P(c_int64)], c_int32),
         "pm_power_spectrum": ([c_void_p, c_void_p, c_int32, P(c_double), P(c_double),
                                P(c_double)], c_int32),
+        "pm_spline_density": ([c_void_p, c_void_p, c_double, c_void_p], c_int32),
+        "pm_spline_qforce": ([c_void_p, c_void_p, c_void_p, c_double, c_void_p], c_int32),
         "pm_timing_enable": ([c_void_p, c_int32], c_int32),
         "pm_timing_read": ([c_void_p, P(PMKernelTime), c_int32, P(c_int32)], c_int32),
         "pm_batch_workspace_bytes": ([P(PMParams), c_int32, P(c_size_t)], c_int32),
@@ -226,6 +229,16 @@ def pm_power_spectrum(ctx: int, pos_ptr: int, nbins: int) -> tuple:
     return list(k)[:nb], list(p)[:nb], list(cnt)[:nb]
 
 
+def pm_spline_density(ctx: int, pos_ptr: int, h: float, delta_ptr: int) -> None:
+    _check(load_library().pm_spline_density(c_void_p(ctx), c_void_p(pos_ptr), float(h),
+                                            c_void_p(delta_ptr)), "pm_spline_density")
+
+
+def pm_spline_qforce(ctx: int, pos_ptr: int, q_ptr: int, h: float, acc_ptr: int) -> None:
+    _check(load_library().pm_spline_qforce(c_void_p(ctx), c_void_p(pos_ptr), c_void_p(q_ptr),
+                                           float(h), c_void_p(acc_ptr)), "pm_spline_qforce")
+
+
 def pm_timing_enable(ctx: int, on: bool) -> None:
     _check(load_library().pm_timing_enable(c_void_p(ctx), int(bool(on))), "pm_timing_enable")
 
@@ -336,6 +349,13 @@ class PMContext:
 
     def power_spectrum(self, pos, nbins=None):
         return pm_power_spectrum(self.ctx, self._pos(pos), self.n // 2 if nbins is None else nbins)
+
+    def spline_density(self, pos, delta_out, h=3.5):
+        pm_spline_density(self.ctx, self._pos(pos), h, self._mesh(delta_out, "delta_out"))
+
+    def spline_qforce(self, pos, q, acc_out, h=3.5):
+        pm_spline_qforce(self.ctx, self._pos(pos), self._mesh(q, "q"), h,
+                         self._vec(acc_out, "acc_out"))
 
     def timing(self, on: bool):
         pm_timing_enable(self.ctx, on)

@@ -18,12 +18,13 @@ namespace {
 enum KernelClass : int {
   kcFill, kcDeposit, kcR2C, kcFftY, kcFftX, kcFftYInv, kcC2R, kcQpot, kcGatherKD, kcKick,
   kcForce, kcReduce, kcKinetic, kcSortCount, kcSortScan, kcSortScatter, kcSortCopy,
-  kcMomentum, kcDiagNodes, kcPower, kcCount
+  kcMomentum, kcDiagNodes, kcPower, kcSpline, kcSplineForce, kcCount
 };
 const char* const kKernelNames[kcCount] = {
     "fill_zero", "deposit", "r2c_z", "fft_y", "fft_x_green", "fft_y_inv", "c2r_z",
     "qpot", "gather_kick_drift", "kick", "force", "reduce", "kinetic", "sort_count",
-    "sort_scan", "sort_scatter", "sort_copy", "momentum_deposit", "diag_nodes", "fft_x_power"};
+    "sort_scan", "sort_scatter", "sort_copy", "momentum_deposit", "diag_nodes", "fft_x_power", "spline_deposit",
+    "spline_qforce"};
 
 struct Timer {
   bool on = false;
@@ -920,6 +921,30 @@ pm_status pm_power_spectrum(pm_ctx* c, const void* d_pos, int32_t nbins, double*
     counts_out[b - 1] = w;
   }
   return PM_OK;
+}
+
+static bool spline_h_ok(const pm_ctx* c, double h) {
+  return isfinite(h) && h >= 0.5 && 2.0 * floor(h) + 2.0 <= (double)c->N && h <= 16.0;
+}
+
+pm_status pm_spline_density(pm_ctx* c, const void* d_pos, double h, float* d_delta) {
+  if (!c || !d_pos || !d_delta) return PM_EINVAL;
+  if (!spline_h_ok(c, h)) return PM_EINVAL;
+  const float mpm = (float)((double)c->ncell / (double)c->np);
+  return timed(c, kcSpline, [&] {
+    return launch_spline_deposit(c->fixed, c->logn, d_pos, c->np, (float)h, mpm, d_delta,
+                                 c->stream);
+  });
+}
+
+pm_status pm_spline_qforce(pm_ctx* c, const void* d_pos, const float* d_q, double h,
+                           float* d_acc) {
+  if (!c || !d_pos || !d_q || !d_acc) return PM_EINVAL;
+  if (!spline_h_ok(c, h)) return PM_EINVAL;
+  return timed(c, kcSplineForce, [&] {
+    return launch_spline_qforce(c->fixed, c->logn, d_pos, c->np, d_q, (float)h, d_acc,
+                                c->stream);
+  });
 }
 
 pm_status pm_timing_enable(pm_ctx* c, int32_t on) {

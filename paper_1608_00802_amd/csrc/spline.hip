@@ -1,0 +1,189 @@
+// The paper's own particle-mesh coupling (Sec. II A): density on the mesh
+// nodes from the cubic spline kernel of Eq. (15) with smoothing length h,
+// Eq. (9), and the quantum force on each particle by the kernel gradient,
+// Eq. (14): a_i = dx^3 sum_j Q_j grad W(x_j - q_i) (dx = 1 in cell units; the
+// sign makes a = -grad Q, the particle derivative of the discrete K_rho).
+// Every node within h of a particle is visited: for h = 3.5 cells a cube of
+// 8^3 candidate nodes, about 180 of them inside the support.
+#include "internal.h"
+
+namespace fdm {
+
+namespace {
+
+// Cell index and fractional offset in [0, 1) of one coordinate.
+template <int LOGN, bool FIXED>
+__device__ __forceinline__ void cell_frac(const void* pos, int64_t at, int& i, float& f) {
+  if constexpr (FIXED) {
+    constexpr int B = 32 - LOGN;
+    const uint32_t u = static_cast<const uint32_t*>(pos)[at];
+    i = (int)(u >> B);
+    f = (float)(u & ((1u << B) - 1u)) * (1.0f / (float)(1u << B));
+  } else {
+    constexpr int MASK = (1 << LOGN) - 1;
+    const float x = static_cast<const float*>(pos)[at];
+    const float fl = floorf(x);
+    i = (int)fl & MASK;
+    f = x - fl;
+  }
+}
+
+// W(r) / c and dW/dr / c' of Eq. (15) for q = r / h <= 1 (c = 8 / (pi h^3),
+// c' = c / h).
+__device__ __forceinline__ float spline_shape(float q) {
+  if (q <= 0.5f) return 1.0f - 6.0f * q * q + 6.0f * q * q * q;
+  const float t = 1.0f - q;
+  return 2.0f * t * t * t;
+}
+__device__ __forceinline__ float spline_slope(float q) {
+  if (q <= 0.5f) return -12.0f * q + 18.0f * q * q;
+  const float t = 1.0f - q;
+  return -6.0f * t * t;
+}
+
+template <int LOGN, bool FIXED>
+__global__ void __launch_bounds__(kBlock) k_spline_deposit(const void* __restrict__ pos,
+                                                           int64_t np, float h, float inv_h,
+                                                           float coef, int lo, int hi,
+                                                           float* __restrict__ rho) {
+  constexpr int N = 1 << LOGN;
+  constexpr int MASK = N - 1;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const float h2 = h * h;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += stride) {
+    int ix, iy, iz;
+    float fx, fy, fz;
+    cell_frac<LOGN, FIXED>(pos, p, ix, fx);
+    cell_frac<LOGN, FIXED>(pos, np + p, iy, fy);
+    cell_frac<LOGN, FIXED>(pos, 2 * np + p, iz, fz);
+    for (int ox = lo; ox <= hi; ++ox) {
+      const float dx = (float)ox - fx;
+      const float dx2 = dx * dx;
+      if (dx2 > h2) continue;
+      const size_t rx = (size_t)((ix + ox) & MASK) * N;
+      for (int oy = lo; oy <= hi; ++oy) {
+        const float dy = (float)oy - fy;
+        const float dxy2 = dx2 + dy * dy;
+        if (dxy2 > h2) continue;
+        const size_t rxy = (rx + ((iy + oy) & MASK)) * N;
+        for (int oz = lo; oz <= hi; ++oz) {
+          const float dz = (float)oz - fz;
+          const float r2 = dxy2 + dz * dz;
+          if (r2 > h2) continue;
+          const float q = sqrtf(r2) * inv_h;
+          unsafeAtomicAdd(&rho[rxy + ((iz + oz) & MASK)], coef * spline_shape(q));
+        }
+      }
+    }
+  }
+}
+
+template <int LOGN, bool FIXED>
+__global__ void __launch_bounds__(kBlock) k_spline_qforce(const void* __restrict__ pos,
+                                                          int64_t np,
+                                                          const float* __restrict__ qmesh,
+                                                          float h, float inv_h, float coef,
+                                                          int lo, int hi,
+                                                          float* __restrict__ acc) {
+  constexpr int N = 1 << LOGN;
+  constexpr int MASK = N - 1;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const float h2 = h * h;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += stride) {
+    int ix, iy, iz;
+    float fx, fy, fz;
+    cell_frac<LOGN, FIXED>(pos, p, ix, fx);
+    cell_frac<LOGN, FIXED>(pos, np + p, iy, fy);
+    cell_frac<LOGN, FIXED>(pos, 2 * np + p, iz, fz);
+    float ax = 0.0f, ay = 0.0f, az = 0.0f;
+    for (int ox = lo; ox <= hi; ++ox) {
+      const float dx = (float)ox - fx;
+      const float dx2 = dx * dx;
+      if (dx2 > h2) continue;
+      const size_t rx = (size_t)((ix + ox) & MASK) * N;
+      for (int oy = lo; oy <= hi; ++oy) {
+        const float dy = (float)oy - fy;
+        const float dxy2 = dx2 + dy * dy;
+        if (dxy2 > h2) continue;
+        const size_t rxy = (rx + ((iy + oy) & MASK)) * N;
+        for (int oz = lo; oz <= hi; ++oz) {
+          const float dz = (float)oz - fz;
+          const float r2 = dxy2 + dz * dz;
+          if (r2 > h2 || r2 == 0.0f) continue;
+          const float r = sqrtf(r2);
+          // Q_j dW/dr / r times the node offset x_j - q_i
+          const float g = qmesh[rxy + ((iz + oz) & MASK)] * spline_slope(r * inv_h) / r;
+          ax = fmaf(g, dx, ax);
+          ay = fmaf(g, dy, ay);
+          az = fmaf(g, dz, az);
+        }
+      }
+    }
+    acc[p] = coef * ax;
+    acc[np + p] = coef * ay;
+    acc[2 * np + p] = coef * az;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_fill_value(float* __restrict__ p, size_t n,
+                                                       float v) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+unsigned spline_grid(int64_t n) {
+  int64_t b = (n + kBlock - 1) / kBlock;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+// Node offsets from the particle's cell that can lie within h: the node
+// j = i + o is within reach when |o - f| <= h for some f in [0, 1).
+void spline_range(float h, int& lo, int& hi) {
+  lo = -(int)floorf(h);
+  hi = (int)floorf(h) + 1;
+}
+
+}  // namespace
+
+hipError_t launch_spline_deposit(bool fixed, int logn, const void* pos, int64_t np, float h,
+                                 float mass_per_mean, float* delta, hipStream_t s) {
+  const size_t ncell = (size_t)1 << (3 * logn);
+  hipLaunchKernelGGL(k_fill_value, dim3(spline_grid((int64_t)ncell)), dim3(kBlock), 0, s, delta,
+                     ncell, -1.0f);
+  int lo, hi;
+  spline_range(h, lo, hi);
+  const float coef = (float)(8.0 / (M_PI * (double)h * h * h)) * mass_per_mean;
+  const unsigned g = spline_grid(np);
+#define L_(LN)                                                                               \
+  if (fixed)                                                                                 \
+    hipLaunchKernelGGL((k_spline_deposit<LN, true>), dim3(g), dim3(kBlock), 0, s, pos, np, h, \
+                       1.0f / h, coef, lo, hi, delta);                                       \
+  else                                                                                       \
+    hipLaunchKernelGGL((k_spline_deposit<LN, false>), dim3(g), dim3(kBlock), 0, s, pos, np, h, \
+                       1.0f / h, coef, lo, hi, delta);
+  FDM_LOGN_SWITCH(logn, L_)
+#undef L_
+  return hipGetLastError();
+}
+
+hipError_t launch_spline_qforce(bool fixed, int logn, const void* pos, int64_t np,
+                                const float* q, float h, float* acc, hipStream_t s) {
+  int lo, hi;
+  spline_range(h, lo, hi);
+  const float coef = (float)(8.0 / (M_PI * (double)h * h * h * h));
+  const unsigned g = spline_grid(np);
+#define L_(LN)                                                                              \
+  if (fixed)                                                                                \
+    hipLaunchKernelGGL((k_spline_qforce<LN, true>), dim3(g), dim3(kBlock), 0, s, pos, np, q, h, \
+                       1.0f / h, coef, lo, hi, acc);                                        \
+  else                                                                                      \
+    hipLaunchKernelGGL((k_spline_qforce<LN, false>), dim3(g), dim3(kBlock), 0, s, pos, np, q, \
+                       h, 1.0f / h, coef, lo, hi, acc);
+  FDM_LOGN_SWITCH(logn, L_)
+#undef L_
+  return hipGetLastError();
+}
+
+}  // namespace fdm

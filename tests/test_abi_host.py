@@ -122,6 +122,8 @@ def test_null_context_calls(lib):
                                    ctypes.byref(cells)) == _lib.PM_EINVAL
     arr = (ctypes.c_double * 4)()
     assert lib.pm_power_spectrum(None, None, 4, arr, arr, arr) == _lib.PM_EINVAL
+    assert lib.pm_spline_density(None, None, 3.5, None) == _lib.PM_EINVAL
+    assert lib.pm_spline_qforce(None, None, None, 3.5, None) == _lib.PM_EINVAL
     assert lib.pm_destroy(None) == _lib.PM_EINVAL
 
 
