@@ -163,6 +163,20 @@ def diag_pass(ctx, pos, vel, p0, a, reps=3):
     for _ in range(reps):
         _, pk, _ = ctx.power_spectrum(pos)
     t3 = time.perf_counter()
+    # the paper's spline coupling (h = 3.5 cells): density, Q, kernel-gradient force
+    n = ctx.n
+    dl = torch.empty(n ** 3, dtype=torch.float32, device=pos.device)
+    qq = torch.empty_like(dl)
+    acc = torch.empty(3, ctx.np, dtype=torch.float32, device=pos.device)
+    ctx.spline_density(pos, dl, 3.5)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    for _ in range(reps):
+        ctx.spline_density(pos, dl, 3.5)
+        ctx.qpot(dl, qq)
+        ctx.spline_qforce(pos, qq, acc, 3.5)
+    torch.cuda.synchronize()
+    t5 = time.perf_counter()
     kern = ctx.timing_read()
     ctx.timing(False)
     np_ = ctx.np
@@ -170,11 +184,17 @@ def diag_pass(ctx, pos, vel, p0, a, reps=3):
            "rms_rel_diff_vs_initial": rms,
            "cells": cells, "kinetic_split_ms": (t1 - t0) * 1e3 / reps,
            "density_rms_diff_ms": (t2 - t1) * 1e3 / reps,
-           "power_spectrum_ms": (t3 - t2) * 1e3 / reps, "power_shells": len(pk)}
-    for name in ("momentum_deposit", "diag_nodes", "fft_x_power"):
+           "power_spectrum_ms": (t3 - t2) * 1e3 / reps, "power_shells": len(pk),
+           "spline_chain_ms": (t5 - t4) * 1e3 / reps}
+    for name in ("momentum_deposit", "diag_nodes", "fft_x_power", "spline_deposit",
+                 "spline_qforce"):
         if name in kern:
             launches, total_ms = kern[name]
             out[name] = {"launches": launches, "avg_ms": round(total_ms / launches, 5)}
+    for name in ("spline_deposit", "spline_qforce"):
+        if name in out:
+            # nodes inside the support of h = 3.5 cells: 4/3 pi h^3 = 179.6 per particle
+            out[name]["kernel_evals_per_s"] = 179.6 * np_ / (out[name]["avg_ms"] * 1e-3)
     if "momentum_deposit" in out:
         out["momentum_deposit"]["fp64_atomics_per_s"] = 8 * np_ / (
             out["momentum_deposit"]["avg_ms"] * 1e-3)

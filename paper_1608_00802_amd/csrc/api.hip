@@ -932,8 +932,8 @@ pm_status pm_spline_density(pm_ctx* c, const void* d_pos, double h, float* d_del
   if (!spline_h_ok(c, h)) return PM_EINVAL;
   const float mpm = (float)((double)c->ncell / (double)c->np);
   return timed(c, kcSpline, [&] {
-    return launch_spline_deposit(c->fixed, c->logn, d_pos, c->np, (float)h, mpm, d_delta,
-                                 c->stream);
+    return launch_spline_deposit(c->fixed, c->logn, d_pos, c->np, (float)h, mpm,
+                                 c->sorted ? &c->tmap : nullptr, d_delta, c->stream);
   });
 }
 

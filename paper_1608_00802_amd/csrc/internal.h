@@ -308,8 +308,10 @@ hipError_t launch_fft_x_power(int logn, const float2* spec, const float2* tw, in
 // ---- spline.hip: the spline kernel of Eq. (15) with smoothing length h
 // (cells); delta (N^3) is filled with -1 and receives the deposit of
 // mass_per_mean = N^3 / Np per particle; acc is [3][np].
+// With tm (sorted context) the deposit sums each tile chunk in LDS first.
 hipError_t launch_spline_deposit(bool fixed, int logn, const void* pos, int64_t np, float h,
-                                 float mass_per_mean, float* delta, hipStream_t s);
+                                 float mass_per_mean, const TileMap* tm, float* delta,
+                                 hipStream_t s);
 hipError_t launch_spline_qforce(bool fixed, int logn, const void* pos, int64_t np,
                                 const float* q, float h, float* acc, hipStream_t s);
 

@@ -78,6 +78,76 @@ __global__ void __launch_bounds__(kBlock) k_spline_deposit(const void* __restric
   }
 }
 
+// Tiled form for a sorted context: one block per chunk of a tile sums the
+// kernel values of its particles into an LDS window covering every node the
+// tile's particles reach (offsets lo .. hi from the tile), then adds the
+// window's non-zero nodes to the mesh; particles that left their tile add to
+// the mesh directly.  Dense clumps then meet in LDS instead of in L2.
+// Windows up to a reach of kSplineReach cells on each side.
+constexpr int kSplineReach = 5;
+template <int LOGN, bool FIXED>
+__global__ void __launch_bounds__(kBlock) k_spline_deposit_tiled(const void* __restrict__ pos,
+                                                                 int64_t np, TileMap tm,
+                                                                 float h, float inv_h,
+                                                                 float coef, int lo, int hi,
+                                                                 float* __restrict__ rho) {
+  constexpr int N = 1 << LOGN;
+  constexpr int MASK = N - 1;
+  constexpr int TX = 1 << tile_lx(LOGN), TY = 1 << tile_ly(LOGN), TZ = 1 << tile_lz(LOGN);
+  constexpr int NTY = N / TY, NTZ = N / TZ;
+  constexpr int MW = (TX + 2 * kSplineReach) * (TY + 2 * kSplineReach) * (TZ + 2 * kSplineReach);
+  __shared__ float win[MW];
+  int t;
+  unsigned p0, p1;
+  if (!chunk_of(tm, t, p0, p1)) return;
+  const int ox = (t / (NTY * NTZ)) * TX, oy = ((t / NTZ) % NTY) * TY, oz = (t % NTZ) * TZ;
+  const int WX = TX + hi - lo, WY = TY + hi - lo, WZ = TZ + hi - lo;
+  for (int c = threadIdx.x; c < WX * WY * WZ; c += kBlock) win[c] = 0.0f;
+  __syncthreads();
+  const float h2 = h * h;
+  for (unsigned p = p0 + threadIdx.x; p < p1; p += kBlock) {
+    int ix, iy, iz;
+    float fx, fy, fz;
+    cell_frac<LOGN, FIXED>(pos, p, ix, fx);
+    cell_frac<LOGN, FIXED>(pos, np + p, iy, fy);
+    cell_frac<LOGN, FIXED>(pos, 2 * np + p, iz, fz);
+    const int rx = (ix - ox) & MASK, ry = (iy - oy) & MASK, rz = (iz - oz) & MASK;
+    const bool inside = rx < TX && ry < TY && rz < TZ;
+    for (int a = lo; a <= hi; ++a) {
+      const float dx = (float)a - fx;
+      const float dx2 = dx * dx;
+      if (dx2 > h2) continue;
+      for (int b = lo; b <= hi; ++b) {
+        const float dy = (float)b - fy;
+        const float dxy2 = dx2 + dy * dy;
+        if (dxy2 > h2) continue;
+        for (int c = lo; c <= hi; ++c) {
+          const float dz = (float)c - fz;
+          const float r2 = dxy2 + dz * dz;
+          if (r2 > h2) continue;
+          const float w = coef * spline_shape(sqrtf(r2) * inv_h);
+          if (inside)
+            atomicAdd(&win[((rx + a - lo) * WY + (ry + b - lo)) * WZ + (rz + c - lo)], w);
+          else
+            unsafeAtomicAdd(&rho[(((size_t)((ix + a) & MASK) * N) + ((iy + b) & MASK)) * N +
+                                 ((iz + c) & MASK)],
+                            w);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < WX * WY * WZ; c += kBlock) {
+    const float v = win[c];
+    if (v != 0.0f) {
+      const int lx = c / (WY * WZ), ly = (c / WZ) % WY, lz = c % WZ;
+      const size_t cell = ((size_t)((ox + lo + lx) & MASK) * N + ((oy + lo + ly) & MASK)) * N +
+                          ((oz + lo + lz) & MASK);
+      unsafeAtomicAdd(&rho[cell], v);
+    }
+  }
+}
+
 template <int LOGN, bool FIXED>
 __global__ void __launch_bounds__(kBlock) k_spline_qforce(const void* __restrict__ pos,
                                                           int64_t np,
@@ -148,13 +218,28 @@ void spline_range(float h, int& lo, int& hi) {
 }  // namespace
 
 hipError_t launch_spline_deposit(bool fixed, int logn, const void* pos, int64_t np, float h,
-                                 float mass_per_mean, float* delta, hipStream_t s) {
+                                 float mass_per_mean, const TileMap* tm, float* delta,
+                                 hipStream_t s) {
   const size_t ncell = (size_t)1 << (3 * logn);
   hipLaunchKernelGGL(k_fill_value, dim3(spline_grid((int64_t)ncell)), dim3(kBlock), 0, s, delta,
                      ncell, -1.0f);
   int lo, hi;
   spline_range(h, lo, hi);
   const float coef = (float)(8.0 / (M_PI * (double)h * h * h)) * mass_per_mean;
+  // the window of a tile holds offsets lo .. hi beyond its cells
+  if (tm && -lo <= kSplineReach && hi <= kSplineReach) {
+    const dim3 gt(tiled_grid(np, tm->tiles));
+#define T_(LN)                                                                              \
+  if (fixed)                                                                                \
+    hipLaunchKernelGGL((k_spline_deposit_tiled<LN, true>), gt, dim3(kBlock), 0, s, pos, np, *tm, \
+                       h, 1.0f / h, coef, lo, hi, delta);                                   \
+  else                                                                                      \
+    hipLaunchKernelGGL((k_spline_deposit_tiled<LN, false>), gt, dim3(kBlock), 0, s, pos, np,    \
+                       *tm, h, 1.0f / h, coef, lo, hi, delta);
+    FDM_LOGN_SWITCH(logn, T_)
+#undef T_
+    return hipGetLastError();
+  }
   const unsigned g = spline_grid(np);
 #define L_(LN)                                                                               \
   if (fixed)                                                                                 \

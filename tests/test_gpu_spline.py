@@ -108,6 +108,37 @@ def test_spline_chain_vs_oracle(pm, gpu, precision):
     assert rel_l2(acc.cpu().numpy().T, ref) < 5e-4
 
 
+@pytest.mark.parametrize("precision", [1, 0])
+@pytest.mark.parametrize("h", [3.5, 4.0])
+def test_spline_density_sorted_with_strays(pm, gpu, precision, h):
+    # a sorted context takes the tiled LDS path; particles moved by up to
+    # 3 cells after the sort leave their tile and add to the mesh directly
+    import torch
+    from synth import to_fixed
+    n = 32
+    st = _clumps(n, 60001, 7)
+    ctx, op = _setup(pm, gpu, n, st.npart, precision)
+    fp32 = precision == 0
+    pos = _positions(st, gpu, fp32)
+    vel = torch.zeros(3, st.npart, dtype=torch.float32, device=gpu)
+    ctx.sort(pos, vel)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(8)
+    x = (positions_cells(pos, n, fp32) + rng.uniform(-3.0, 3.0, (st.npart, 3))) % n
+    if fp32:
+        xf = np.ascontiguousarray(x.T.astype(np.float32))
+        xf[xf >= np.float32(n)] = 0.0
+        pos.copy_(torch.from_numpy(xf))
+    else:
+        pos.copy_(torch.from_numpy(to_fixed(x, n).view(np.int32)))
+    delta = torch.empty(n ** 3, dtype=torch.float32, device=gpu)
+    ctx.spline_density(pos, delta, h)
+    rho = oracle.spline_deposit(positions_cells(pos, n, fp32), op, h)
+    torch.cuda.synchronize()
+    got = 1.0 + delta.cpu().numpy().astype(np.float64).reshape(n, n, n)
+    assert rel_l2(got, rho) < 1e-5
+
+
 def test_spline_full_size_sampled(pm, gpu):
     # 256^3 particles on a 256^3 mesh: mean density one to the kernel's
     # discretisation, and the force of 400 sampled particles against the
