@@ -111,8 +111,8 @@ def test_spline_chain_vs_oracle(pm, gpu, precision):
 @pytest.mark.parametrize("precision", [1, 0])
 @pytest.mark.parametrize("h", [3.5, 4.0])
 def test_spline_density_sorted_with_strays(pm, gpu, precision, h):
-    # a sorted context takes the tiled LDS path; particles moved by up to
-    # 3 cells after the sort leave their tile and add to the mesh directly
+    # a sorted context takes the tiled LDS paths; particles moved by up to
+    # 3 cells after the sort leave their tile and use the mesh directly
     import torch
     from synth import to_fixed
     n = 32
@@ -133,10 +133,19 @@ def test_spline_density_sorted_with_strays(pm, gpu, precision, h):
         pos.copy_(torch.from_numpy(to_fixed(x, n).view(np.int32)))
     delta = torch.empty(n ** 3, dtype=torch.float32, device=gpu)
     ctx.spline_density(pos, delta, h)
-    rho = oracle.spline_deposit(positions_cells(pos, n, fp32), op, h)
+    xs = positions_cells(pos, n, fp32)
+    rho = oracle.spline_deposit(xs, op, h)
     torch.cuda.synchronize()
     got = 1.0 + delta.cpu().numpy().astype(np.float64).reshape(n, n, n)
     assert rel_l2(got, rho) < 1e-5
+    # the tiled force (Q staged per tile chunk in LDS), strays from the mesh
+    q32 = oracle.qpot(rho, op).astype(np.float32)
+    qd = torch.from_numpy(q32.ravel().copy()).to(gpu)
+    acc = torch.empty(3, st.npart, dtype=torch.float32, device=gpu)
+    ctx.spline_qforce(pos, qd, acc, h)
+    ref = oracle.spline_qforce(xs, q32.astype(np.float64), op, h)
+    torch.cuda.synchronize()
+    assert rel_l2(acc.cpu().numpy().T, ref) < 1e-4
 
 
 def test_spline_full_size_sampled(pm, gpu):
