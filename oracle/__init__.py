@@ -40,4 +40,6 @@ from .pm import (  # noqa: F401
     spline_deposit,
     spline_qforce,
     spline_kinetic_rho,
+    spline_forces,
+    spline_run,
 )

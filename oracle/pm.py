@@ -547,3 +547,31 @@ def spline_kinetic_rho(pos, p: Params, h: float) -> float:
     for ax in range(3):
         tot += float(np.sum((np.roll(s, -1, axis=ax) - s) ** 2))
     return p.hbar_m ** 2 / 2.0 * p.dx * tot
+
+
+def spline_forces(pos, p: Params, h: float):
+    """(g_phi, g_Q) with the paper's own coupling (Sec. II A): the density of
+    Eq. (9) with the spline of Eq. (15) feeds both the gravity solve and Q;
+    gravity is -grad(phi) interpolated by cloud-in-cell (the host code's PM
+    interpolation), the quantum force is the kernel gradient of Eq. (14)."""
+    rho = spline_deposit(pos, p, h)
+    phi = poisson(rho - 1.0, p)
+    g_phi = interp_cic(grad_central(phi, p), pos, p)
+    if p.hbar_m != 0.0:
+        g_q = spline_qforce(pos, qpot(rho, p), p, h)
+    else:
+        g_q = np.zeros_like(g_phi)
+    return g_phi, g_q
+
+
+def spline_run(pos, vel, p: Params, times, h: float):
+    """kdk_step's leapfrog with spline_forces, through the schedule ``times``."""
+    x, v = pos, vel
+    acc = spline_forces(x, p, h)
+    for t0, t1 in zip(times[:-1], times[1:]):
+        (fg0, fq0), fd, (fg1, fq1) = step_factors(t0, t1, p)
+        v = v + acc[0] * fg0 + acc[1] * fq0
+        x = _wrap(x + v * fd, p.box)
+        acc = spline_forces(x, p, h)
+        v = v + acc[0] * fg1 + acc[1] * fq1
+    return x, v
