@@ -266,6 +266,19 @@ pm_status pm_spline_density(pm_ctx* ctx, const void* d_pos, double h, float* d_d
 pm_status pm_spline_qforce(pm_ctx* ctx, const void* d_pos, const float* d_q, double h,
                            float* d_acc);
 
+/* nsteps kick-drift-kick steps through times[0..nsteps] (as pm_step) with the
+ * paper's own coupling (Sec. II A): every force evaluation deposits the
+ * spline density (pm_spline_density), solves gravity on it (FFT Poisson,
+ * -grad phi interpolated by cloud-in-cell, as the host code's PM does) and
+ * takes Q on it with the kernel-gradient force (pm_spline_qforce).  Comoving
+ * factors as pm_step (Q's kick carries 1/a^3, gravity's 1/a^2).  Unfused and
+ * unsorted: no window halos, no merged half-kicks, two extra [3][Np] float
+ * arrays in the workspace's particle buffers.  Enqueues only; positions and
+ * velocities are synchronised on entry and on return.  Leaves no
+ * cloud-in-cell field valid (later calls recompute them). */
+pm_status pm_spline_step(pm_ctx* ctx, void* d_pos, float* d_vel, const double* times,
+                         int32_t nsteps, double h);
+
 /* Per-kernel timing (observability).  While enabled, every kernel the
  * context launches is bracketed by two HIP events recorded on its stream.
  * pm_timing_enable(ctx, 1) clears the counters and starts recording;

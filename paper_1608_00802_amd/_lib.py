@@ -28,7 +28,7 @@ def PM_SORT_EVERY(k: int) -> int:
 EXPORTED = ("pm_workspace_bytes", "pm_init", "pm_deposit", "pm_poisson", "pm_qpot",
             "pm_force", "pm_step", "pm_sort", "pm_energy", "pm_kinetic_split",
             "pm_density_rms_diff", "pm_power_spectrum", "pm_spline_density",
-            "pm_spline_qforce", "pm_timing_enable", "pm_timing_read",
+            "pm_spline_qforce", "pm_spline_step", "pm_timing_enable", "pm_timing_read",
             "pm_batch_workspace_bytes", "pm_batch_init", "pm_batch_slot_offset",
             "pm_batch_set_slot", "pm_batch_step", "pm_batch_destroy", "pm_destroy",
             "pm_strerror")
@@ -105,6 +105,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                P(c_double)], c_int32),
         "pm_spline_density": ([c_void_p, c_void_p, c_double, c_void_p], c_int32),
         "pm_spline_qforce": ([c_void_p, c_void_p, c_void_p, c_double, c_void_p], c_int32),
+        "pm_spline_step": ([c_void_p, c_void_p, c_void_p, P(c_double), c_int32, c_double],
+                           c_int32),
         "pm_timing_enable": ([c_void_p, c_int32], c_int32),
         "pm_timing_read": ([c_void_p, P(PMKernelTime), c_int32, P(c_int32)], c_int32),
         "pm_batch_workspace_bytes": ([P(PMParams), c_int32, P(c_size_t)], c_int32),
@@ -239,6 +241,13 @@ def pm_spline_qforce(ctx: int, pos_ptr: int, q_ptr: int, h: float, acc_ptr: int)
                                            float(h), c_void_p(acc_ptr)), "pm_spline_qforce")
 
 
+def pm_spline_step(ctx: int, pos_ptr: int, vel_ptr: int, times, h: float) -> None:
+    t = [float(x) for x in times]
+    arr = (c_double * len(t))(*t)
+    _check(load_library().pm_spline_step(c_void_p(ctx), c_void_p(pos_ptr), c_void_p(vel_ptr),
+                                         arr, len(t) - 1, float(h)), "pm_spline_step")
+
+
 def pm_timing_enable(ctx: int, on: bool) -> None:
     _check(load_library().pm_timing_enable(c_void_p(ctx), int(bool(on))), "pm_timing_enable")
 
@@ -356,6 +365,11 @@ class PMContext:
     def spline_qforce(self, pos, q, acc_out, h=3.5):
         pm_spline_qforce(self.ctx, self._pos(pos), self._mesh(q, "q"), h,
                          self._vec(acc_out, "acc_out"))
+
+    def spline_step(self, pos, vel, times, h=3.5):
+        if len(times) < 2 or any(not math.isfinite(float(t)) for t in times):
+            raise ValueError("times: need at least two finite values")
+        pm_spline_step(self.ctx, self._pos(pos), self._vec(vel, "vel"), times, h)
 
     def timing(self, on: bool):
         pm_timing_enable(self.ctx, on)

@@ -947,6 +947,66 @@ pm_status pm_spline_qforce(pm_ctx* c, const void* d_pos, const float* d_q, doubl
   });
 }
 
+pm_status pm_spline_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times,
+                         int32_t nsteps, double h) {
+  if (!c || !d_pos || !d_vel || !times || nsteps < 1) return PM_EINVAL;
+  if (!spline_h_ok(c, h)) return PM_EINVAL;
+  for (int s = 0; s <= nsteps; ++s) {
+    if (!isfinite(times[s]) || (c->p.comoving && !(times[s] > 0.0))) return PM_EINVAL;
+    if (s > 0 && !(times[s] > times[s - 1])) return PM_EINVAL;
+  }
+  // accelerations at the current positions: -grad phi (CIC) and the kernel
+  // gradient of Q, [3][Np] floats each in the particle copy buffers
+  float* gphi = reinterpret_cast<float*>(c->pos_tmp);
+  float* gq = c->vel_tmp;
+  const float mpm = (float)((double)c->ncell / (double)c->np);
+  auto forces = [&]() -> pm_status {
+    PM_TRY(timed(c, kcSpline, [&] {
+      return launch_spline_deposit(c->fixed, c->logn, d_pos, c->np, (float)h, mpm,
+                                   c->sorted ? &c->tmap : nullptr, c->delta, c->stream);
+    }));
+    PM_TRY(run_poisson(c, kSrcDelta, c->delta));
+    PM_TRY(timed(c, kcForce, [&] {
+      return launch_force(c->fixed, false, c->logn, d_pos, c->phi, c->q, c->np, 1.0f, 0.0f,
+                          gphi, c->stream);
+    }));
+    if (!c->has_q)
+      // 16-byte multiple: the buffer is a 256-byte aligned region of at least 12 Np bytes
+      return timed(c, kcFill, [&] {
+        return launch_fill_zero(gq, (12 * (size_t)c->np + 15) & ~(size_t)15, c->stream);
+      });
+    PM_TRY(run_qpot(c, c->delta, false, kOutQ));
+    return timed(c, kcSplineForce, [&] {
+      return launch_spline_qforce(c->fixed, c->logn, d_pos, c->np, c->q, (float)h, gq,
+                                  c->stream);
+    });
+  };
+  auto kick_by = [&](const Kick& k) {
+    return timed(c, kcKick, [&] {
+      return launch_spline_kick(d_vel, gphi, gq, c->np, (float)k.g, (float)k.q, c->stream);
+    });
+  };
+  c->fields_at_pos = false;
+  PM_TRY(forces());
+  for (int s = 0; s < nsteps; ++s) {
+    const double t0 = times[s], t1 = times[s + 1], tm = midpoint(c->p, t0, t1);
+    PM_TRY(kick_by(kick(c->p, t0, tm)));
+    PM_TRY(timed(c, kcGatherKD, [&] {
+      return launch_spline_drift(c->fixed, c->logn, d_pos, d_vel, c->np, drift(c->p, t0, t1),
+                                 c->stream);
+    }));
+    PM_TRY(forces());
+    PM_TRY(kick_by(kick(c->p, tm, t1)));
+  }
+  // delta holds the spline contrast and phi, Q its fields; none of them is
+  // what the cloud-in-cell calls expect
+  c->have_delta = false;
+  c->have_phi = false;
+  c->have_q = false;
+  if (!c->has_q) PM_TRY(dev(launch_fill_zero(c->q, 4 * c->ncell, c->stream)));
+  return PM_OK;
+}
+
 pm_status pm_timing_enable(pm_ctx* c, int32_t on) {
   if (!c) return PM_EINVAL;
   Timer& t = c->timer;

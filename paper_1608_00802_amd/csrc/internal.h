@@ -314,6 +314,11 @@ hipError_t launch_spline_deposit(bool fixed, int logn, const void* pos, int64_t 
                                  hipStream_t s);
 hipError_t launch_spline_qforce(bool fixed, int logn, const void* pos, int64_t np,
                                 const float* q, float h, float* acc, hipStream_t s);
+// The spline step's half-kick (v += fg g_phi + fq g_q) and drift (x += fd v).
+hipError_t launch_spline_kick(float* vel, const float* gphi, const float* gq, int64_t np,
+                              float fg, float fq, hipStream_t s);
+hipError_t launch_spline_drift(bool fixed, int logn, void* pos, const float* vel, int64_t np,
+                               double fd, hipStream_t s);
 
 // ---- diag.hip
 // Grid diagnostics: node momenta of one velocity component (FP64 atomics into

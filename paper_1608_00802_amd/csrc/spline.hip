@@ -195,6 +195,39 @@ __global__ void __launch_bounds__(kBlock) k_spline_qforce(const void* __restrict
   }
 }
 
+// Half-kick of the spline step: v += fg g_phi + fq g_q, arrays [3][np].
+__global__ void __launch_bounds__(kBlock) k_spline_kick(float* __restrict__ vel,
+                                                        const float* __restrict__ gphi,
+                                                        const float* __restrict__ gq, int64_t n,
+                                                        float fg, float fq) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    vel[i] = fmaf(fq, gq[i], fmaf(fg, gphi[i], vel[i]));
+}
+
+// Drift of the spline step: x += fd v, periodic.  Fixed point: the
+// displacement rounded to the nearest unit, 32-bit wrap; float: wrapped into
+// [0, N).
+template <int LOGN, bool FIXED>
+__global__ void __launch_bounds__(kBlock) k_spline_drift(void* __restrict__ pos,
+                                                         const float* __restrict__ vel,
+                                                         int64_t n, double fd) {
+  constexpr int N = 1 << LOGN;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    if constexpr (FIXED) {
+      const double units = (double)vel[i] * fd * (double)(1ull << (32 - LOGN));
+      uint32_t* u = static_cast<uint32_t*>(pos);
+      u[i] += (uint32_t)(int64_t)llrint(units);
+    } else {
+      float* x = static_cast<float*>(pos);
+      float v = fmaf((float)fd, vel[i], x[i]);
+      v -= (float)N * floorf(v * (1.0f / (float)N));
+      x[i] = v >= (float)N ? 0.0f : v;
+    }
+  }
+}
+
 __global__ void __launch_bounds__(kBlock) k_fill_value(float* __restrict__ p, size_t n,
                                                        float v) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -266,6 +299,28 @@ hipError_t launch_spline_qforce(bool fixed, int logn, const void* pos, int64_t n
   else                                                                                      \
     hipLaunchKernelGGL((k_spline_qforce<LN, false>), dim3(g), dim3(kBlock), 0, s, pos, np, q, \
                        h, 1.0f / h, coef, lo, hi, acc);
+  FDM_LOGN_SWITCH(logn, L_)
+#undef L_
+  return hipGetLastError();
+}
+
+hipError_t launch_spline_kick(float* vel, const float* gphi, const float* gq, int64_t np,
+                              float fg, float fq, hipStream_t s) {
+  const int64_t n = 3 * np;
+  hipLaunchKernelGGL(k_spline_kick, dim3(spline_grid(n)), dim3(kBlock), 0, s, vel, gphi, gq, n,
+                     fg, fq);
+  return hipGetLastError();
+}
+
+hipError_t launch_spline_drift(bool fixed, int logn, void* pos, const float* vel, int64_t np,
+                               double fd, hipStream_t s) {
+  const int64_t n = 3 * np;
+  const unsigned g = spline_grid(n);
+#define L_(LN)                                                                               \
+  if (fixed)                                                                                 \
+    hipLaunchKernelGGL((k_spline_drift<LN, true>), dim3(g), dim3(kBlock), 0, s, pos, vel, n, fd); \
+  else                                                                                       \
+    hipLaunchKernelGGL((k_spline_drift<LN, false>), dim3(g), dim3(kBlock), 0, s, pos, vel, n, fd);
   FDM_LOGN_SWITCH(logn, L_)
 #undef L_
   return hipGetLastError();
