@@ -75,10 +75,13 @@ def plan_chunk(a: float, count: int, hm_cells: float, vmax: float, omega_m: floa
 def run(n: int = 256, box: float = 1.4, m_ev: float = 2.5e-22, seed: int = 1,
         omega_m: float = 0.25, h: float = 0.7, a_start: float = A_START, a_end: float = A_END,
         chunk: int = 10, device=None, keep_states: bool = False, max_steps: int = 4000,
-        progress=None, ics: str = "cdm") -> dict:
+        progress=None, ics: str = "cdm", coupling: str = "cic", h_spline: float = 3.5) -> dict:
     """ics = "cdm": initial power with the CDM transfer function (the first
     test); "fdm": with the FDM transfer function of the same boson mass
-    (the second test, Fig. 6), both runs still starting from one state."""
+    (the second test, Fig. 6), both runs still starting from one state.
+    coupling = "cic": the fused cloud-in-cell step (pm_step); "spline": the
+    paper's own coupling (pm_spline_step, smoothing length h_spline cells),
+    the particles re-sorted by tile every chunk."""
     import torch
 
     import paper_1608_00802_amd as pm
@@ -87,6 +90,8 @@ def run(n: int = 256, box: float = 1.4, m_ev: float = 2.5e-22, seed: int = 1,
     dev = device if device is not None else torch.device("cuda:0")
     if ics not in ("cdm", "fdm"):
         raise ValueError("ics: 'cdm' or 'fdm'")
+    if coupling not in ("cic", "spline"):
+        raise ValueError("coupling: 'cic' or 'spline'")
     st = zeldovich_state(n, box, a_start, seed, m_ev=m_ev if ics == "fdm" else None, om=omega_m,
                          h=h)
     hm = hbar_over_m(m_ev, h)
@@ -113,8 +118,13 @@ def run(n: int = 256, box: float = 1.4, m_ev: float = 2.5e-22, seed: int = 1,
         vmax = 2.0 * max(float(vel_f.abs().max().item()), float(vel_c.abs().max().item()))
         nxt = plan_chunk(times[-1], chunk, hm_cells, vmax, omega_m, a_end)
         seg = [times[-1]] + nxt
-        ctx_f.step(pos_f, vel_f, seg, flags=flags)
-        ctx_c.step(pos_c, vel_c, seg, flags=flags)
+        if coupling == "spline":
+            for ctx, p_, v_ in ((ctx_f, pos_f, vel_f), (ctx_c, pos_c, vel_c)):
+                ctx.sort(p_, v_)
+                ctx.spline_step(p_, v_, seg, h_spline)
+        else:
+            ctx_f.step(pos_f, vel_f, seg, flags=flags)
+            ctx_c.step(pos_c, vel_c, seg, flags=flags)
         flags = pm.PM_SORT_AUTO | pm.PM_CONTINUE
         times += nxt
         if progress is not None and (len(times) - 1) % (10 * chunk) < chunk:
@@ -127,7 +137,7 @@ def run(n: int = 256, box: float = 1.4, m_ev: float = 2.5e-22, seed: int = 1,
     p_f, p_c, p_start = np.asarray(p_f), np.asarray(p_c), np.asarray(p_start)
     out = {
         "n": n, "box_mpch": box, "m_ev": m_ev, "hbar_over_m": hm, "omega_m": omega_m,
-        "ics": ics,
+        "ics": ics, "coupling": coupling,
         "seed": seed, "a_start": a_start, "a_end": times[-1], "steps": len(times) - 1,
         "reached_a_end": times[-1] >= a_end,
         "wall_s": wall, "finite": bool(torch.isfinite(vel_f).all().item()
@@ -176,11 +186,13 @@ def main(argv=None):
     ap.add_argument("--ics", choices=("cdm", "fdm"), default="cdm",
                     help="transfer function of the initial power (first or second test)")
     ap.add_argument("--z-end", type=float, default=1.0 / A_END - 1.0)
+    ap.add_argument("--coupling", choices=("cic", "spline"), default="cic",
+                    help="fused cloud-in-cell step, or the paper's spline kernel (h = 3.5 cells)")
     ap.add_argument("--max-steps", type=int, default=4000,
                     help="stop there (the velocity bound shortens the steps of a run gone unstable)")
     args = ap.parse_args(argv)
     res = run(args.n, args.box, args.m_ev, args.seed, a_end=1.0 / (1.0 + args.z_end),
-              max_steps=args.max_steps, ics=args.ics,
+              max_steps=args.max_steps, ics=args.ics, coupling=args.coupling,
               progress=lambda msg: print(msg, file=sys.stderr, flush=True))
     res.pop("times")
     res["summary"] = summary(res)
