@@ -11,18 +11,19 @@ it.  Every step and every spectrum runs through the library (pm_step,
 pm_power_spectrum, pm_density_rms_diff); this module only plans the steps and
 reports.
 
-With the cloud-in-cell deposit and mesh gradients the FDM run also develops
-growth near the grid scale (k above about half the mesh Nyquist wavenumber)
-that the paper's wide spline kernel does not have; the suppression window
-around k_J is reproduced at every mesh size.  The velocity bound then
-shortens the steps, hence the step cap.
+With the cloud-in-cell deposit and mesh gradients (--coupling cic) the FDM
+run also develops growth near the grid scale (k above about half the mesh
+Nyquist wavenumber) on fine meshes, and the velocity bound then shortens the
+steps, hence the step cap; the paper's own spline coupling (--coupling
+spline) stays stable there.
 
 Units follow the library's comoving convention: lengths in Mpc/h, time in
 1/H0, hbar/m in (Mpc/h)^2 H0.  The paper's box of L = 2 Mpc is 1.4 Mpc/h at
 h = 0.7; its cosmology is Omega_m = 0.25, Omega_Lambda = 0.75.
 
     python -m paper_1608_00802_amd.fdm_vs_cdm --n 256
-    python -m paper_1608_00802_amd.fdm_vs_cdm --ics fdm --box 7.0 --z-end 2.38 --n 256
+    python -m paper_1608_00802_amd.fdm_vs_cdm --ics fdm --box 1.75 --z-end 2.38 --n 512 \
+        --coupling spline
 """
 
 from __future__ import annotations
