@@ -142,6 +142,45 @@ def run_gpu(st, n, steps, warmup, a_start, kernel_pass=True, sort_every=10, fp32
     return out
 
 
+def spline_section(st, n, box, steps=5, warmup=2, h=3.5):
+    """The step with the paper's own coupling (pm_spline_step, h = 3.5 cells)
+    on the same Zel'dovich box, sorted by tile first; wall time of `steps`
+    steps after `warmup`, and its per-kernel times."""
+    import numpy as np
+    import torch
+
+    import paper_1608_00802_amd as pm
+    from synth import comoving_code_params
+
+    dev = torch.device("cuda:0")
+    hm = comoving_code_params(box, n, 1e-22, 0.7)["hbar_m_cells"] * (box / n) ** 2
+    lp = pm.make_params(n, st.npart, box, precision=pm.PM_FIXED32, comoving=True, omega_m=0.3,
+                        omega_l=0.7, h0=1.0, hbar_over_m=hm, rho_floor=1e-6, rho_fp64_below=1e-3)
+    ctx = pm.PMContext(lp, device=dev)
+    pos = torch.from_numpy(st.pos_fixed.view(np.int32).copy()).to(dev)
+    vel = torch.from_numpy(st.vel32.copy()).to(dev)
+    ctx.sort(pos, vel)
+    times = [0.01 * math.exp(i * DLNA) for i in range(warmup + 2 * steps + 1)]
+    ctx.spline_step(pos, vel, times[: warmup + 1], h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.spline_step(pos, vel, times[warmup: warmup + steps + 1], h)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.timing(True)
+    ctx.spline_step(pos, vel, times[warmup + steps:], h)
+    kern = ctx.timing_read()
+    ctx.timing(False)
+    out = {"form": "pm_spline_step: spline density (h = 3.5 cells) for gravity and Q, "
+                   "kernel-gradient Q force, unfused KDK",
+           "value": st.npart * steps / wall, "ms_per_step": wall * 1e3 / steps,
+           "finite": bool(torch.isfinite(vel).all().item()),
+           "kernels": {k: {"launches": v[0], "avg_ms": round(v[1] / v[0], 4)}
+                       for k, v in kern.items()}}
+    ctx.close()
+    return out
+
+
 def diag_pass(ctx, pos, vel, p0, a, reps=3):
     """Grid diagnostics of the state left by the timed steps (after the timed
     region), sorted by tile first so that the momentum deposit takes its
@@ -324,6 +363,8 @@ def main():
     ap.add_argument("--no-evolved", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-spline", action="store_true",
+                    help="skip the step with the spline kernel")
     ap.add_argument("--no-diag", action="store_true",
                     help="skip the grid diagnostics after the evolved run")
     ap.add_argument("--serve-requests", type=int, default=48)
@@ -421,6 +462,8 @@ def main():
             line["evolved"]["kernels"] = kernel_table(re_["kernels"], n, re_["np"], args.steps)
         if "diag" in re_:
             line["evolved"]["diagnostics"] = re_["diag"]
+    if not args.no_spline:
+        line["spline_form"] = spline_section(st, n, args.box)
     if trace is not None:
         line["serving"] = serve_section(trace, ics)
         del ics
