@@ -87,9 +87,9 @@ def test_spline_density_and_force_vs_oracle(pm, gpu, precision, case, h):
 
 @pytest.mark.parametrize("precision", [1, 0])
 def test_spline_chain_vs_oracle(pm, gpu, precision):
-    # density -> pm_qpot -> force, against the oracle's chain (n = 64)
+    # density -> pm_qpot -> force, against the oracle's chain (n = 32)
     import torch
-    n = 64
+    n = 32
     st = _jittered(n, 3)
     ctx, op = _setup(pm, gpu, n, st.npart, precision)
     fp32 = precision == 0
