@@ -258,7 +258,7 @@ pm_status pm_power_spectrum(pm_ctx* ctx, const void* d_pos, int32_t nbins,
  * every particle by the kernel gradient, Eq. (14): a_i = sum_j Q_j
  * grad W(x_j - q_i) (cell units, dx = 1), with the sign that makes it
  * -grad Q, i.e. minus the particle derivative of the discrete K_rho of
- * Eq. (12) whose node derivative is Q.  d_q is float [N^3] as from pm_qpot.
+ * Eq. (11) whose node derivative is Q.  d_q is float [N^3] as from pm_qpot.
  *
  * Both enqueue only.  PM_EINVAL for null pointers or h outside
  * [0.5, 16] or so wide that 2 floor(h) + 2 > N. */

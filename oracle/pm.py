@@ -539,7 +539,7 @@ def spline_qforce(pos, q, p: Params, h: float) -> np.ndarray:
 
 
 def spline_kinetic_rho(pos, p: Params, h: float) -> float:
-    """K_rho of Eq. (12) on the spline density per unit mass density
+    """K_rho of Eq. (11) on the spline density per unit mass density
     (rho in units of the mean), with forward differences, the exact
     conjugate of the 7-point Laplacian in Q; no floor (rho > 0 assumed)."""
     s = np.sqrt(spline_deposit(pos, p, h))

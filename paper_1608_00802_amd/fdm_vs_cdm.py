@@ -5,7 +5,7 @@ to z = 18.5; second test: the FDM transfer function of the boson mass, to
 z = 2.38) are evolved twice: once with quantum pressure (boson mass m, comoving
 Q of Eq. (18)) and once without (hbar/m = 0), on one step schedule.  The
 power spectra of both runs are then compared shell by shell, (P_FDM -
-P_CDM) / P_CDM, beside the quantum Jeans wavenumber k_J(a) of Eq. (20) at the
+P_CDM) / P_CDM, beside the quantum Jeans wavenumber k_J(a) of Eq. (19) at the
 start and at the end: growth is suppressed above k_J and unchanged well below
 it.  Every step and every spectrum runs through the library (pm_step,
 pm_power_spectrum, pm_density_rms_diff); this module only plans the steps and
@@ -43,7 +43,7 @@ A_END = 1.0 / 19.5        # z = 18.5
 
 
 def jeans_k(a: float, hm: float, omega_m: float) -> float:
-    """Eq. (20) in comoving units: k_J = (16 pi G rho_bar a)^(1/4) (m/hbar)^(1/2)
+    """Eq. (19) in comoving units: k_J = (16 pi G rho_bar a)^(1/4) (m/hbar)^(1/2)
     with 4 pi G rho_bar = (3/2) Omega_m H0^2, so k_J = (6 Omega_m a)^(1/4) /
     sqrt(hbar/m) for hbar/m in (Mpc/h)^2 H0; returns h/Mpc."""
     return (6.0 * omega_m * a) ** 0.25 / math.sqrt(hm)

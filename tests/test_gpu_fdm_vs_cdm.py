@@ -4,7 +4,7 @@ schedule, and the qualitative result the paper reports: equal power well
 below the quantum Jeans scale, suppressed growth above it.
 
 32^3 particles in a 0.7 Mpc/h box (the cell size of the paper's 2 Mpc box,
-1.4 Mpc/h, at 64^3), m = 2.5e-22 eV, z = 100 to 18.5: k_J of Eq. (20) moves
+1.4 Mpc/h, at 64^3), m = 2.5e-22 eV, z = 100 to 18.5: k_J of Eq. (19) moves
 from about 47 to 72 h/Mpc, inside the mesh's shells (9 to 144 h/Mpc).
 """
 

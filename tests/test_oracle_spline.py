@@ -6,7 +6,7 @@ Against: the kernel's normalisation as a continuous integral and its
 continuity, a numerical derivative of W, a brute-force double loop with the
 periodic minimum image, the uniform density of a node lattice, and -- the
 strongest pin -- the force as minus the particle derivative of the discrete
-energy K_rho of Eq. (12) (finite differences of the energy, which also fixes
+energy K_rho of Eq. (11) (finite differences of the energy, which also fixes
 the sign read for Eq. (14) and its dx^3 and m factors).  CPU only.
 """
 
@@ -102,7 +102,7 @@ def test_s5_force_is_minus_energy_gradient():
 
 def test_s6_spline_leapfrog_conserves_the_discrete_energy():
     # Sec. II A: the kernel-gradient force conserves K_v + K_rho of Eqs. (8),
-    # (12) by construction, so the leapfrog's energy error (gravity off) falls
+    # (11) by construction, so the leapfrog's energy error (gravity off) falls
     # as dt^2: a factor near 4 per halving of the step
     n = 12
     p = Params(n=n, box=float(n), S=0.0, hbar_m=0.8)
