@@ -33,8 +33,8 @@
  *   sums of CIC weights (PM_FP32, first 4 N^3 bytes).  Everything else in the
  *   workspace is private.
  * Asynchrony.  All calls except pm_workspace_bytes, pm_energy,
- *   pm_kinetic_split, pm_density_rms_diff, pm_power_spectrum and pm_destroy
- *   only enqueue work on the context's HIP stream and return.  Argument errors
+ *   pm_kinetic_split, pm_density_rms_diff, pm_power_spectrum, pm_spline_energy
+ *   and pm_destroy only enqueue work on the context's HIP stream and return.  Argument errors
  *   are reported synchronously; a kernel launch error is reported as
  *   PM_EDEVICE.  A context is bound to one stream and is not thread-safe;
  *   distinct contexts on distinct workspaces are independent.
@@ -278,6 +278,15 @@ pm_status pm_spline_qforce(pm_ctx* ctx, const void* d_pos, const float* d_q, dou
  * cloud-in-cell field valid (later calls recompute them). */
 pm_status pm_spline_step(pm_ctx* ctx, void* d_pos, float* d_vel, const double* times,
                          int32_t nsteps, double h);
+
+/* K, W, U, E as pm_energy, with the density of pm_spline_density (smoothing
+ * length h cells) in place of cloud-in-cell: the energy that the kernel-
+ * gradient force of pm_spline_step conserves (with gravity off) up to the
+ * leapfrog's second-order error (Sec. II A).  U takes forward differences
+ * of sqrt(max(rho, floor)), W = sum delta phi / 2a.  Blocks until done;
+ * uses the field area as scratch like the other diagnostics. */
+pm_status pm_spline_energy(pm_ctx* ctx, const void* d_pos, const float* d_vel, double h,
+                           double a, pm_energies* out);
 
 /* Per-kernel timing (observability).  While enabled, every kernel the
  * context launches is bracketed by two HIP events recorded on its stream.

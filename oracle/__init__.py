@@ -42,4 +42,5 @@ from .pm import (  # noqa: F401
     spline_kinetic_rho,
     spline_forces,
     spline_run,
+    spline_energies,
 )

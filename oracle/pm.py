@@ -575,3 +575,22 @@ def spline_run(pos, vel, p: Params, times, h: float):
         acc = spline_forces(x, p, h)
         v = v + acc[0] * fg1 + acc[1] * fq1
     return x, v
+
+
+def spline_energies(pos, vel, p: Params, h: float, a: float = 1.0) -> dict:
+    """energies() with the density of Eq. (9) and the spline of Eq. (15):
+    K of Eq. (8), W = 1/(2a) sum delta phi dx^3, and U the forward-difference
+    K_rho of Eq. (11) of sqrt(max(rho, floor)) with the 1/a^2 of Eq. (18)."""
+    npart = pos.shape[0]
+    mp = p.box ** 3 / npart
+    rho = spline_deposit(pos, p, h)
+    delta = rho - 1.0
+    phi = poisson(delta, p)
+    kin = 0.5 * mp * float(np.sum(vel * vel)) / a ** 2
+    wg = 0.5 * float(np.sum(delta * phi)) * p.dx ** 3 / a
+    s = np.sqrt(np.maximum(rho, p.rho_floor))
+    fwd = 0.0
+    for ax in range(3):
+        fwd += float(np.sum((np.roll(s, -1, axis=ax) - s) ** 2))
+    u_f = p.hbar_m ** 2 / 2.0 / a ** 2 * p.dx * fwd
+    return {"K": kin, "W": wg, "U": u_f, "E": kin + wg + u_f}

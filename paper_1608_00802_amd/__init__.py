@@ -32,6 +32,7 @@ from ._lib import (  # noqa: F401
     pm_spline_density,
     pm_spline_qforce,
     pm_spline_step,
+    pm_spline_energy,
     pm_step,
     pm_timing_enable,
     pm_timing_read,

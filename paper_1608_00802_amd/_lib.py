@@ -28,7 +28,7 @@ def PM_SORT_EVERY(k: int) -> int:
 EXPORTED = ("pm_workspace_bytes", "pm_init", "pm_deposit", "pm_poisson", "pm_qpot",
             "pm_force", "pm_step", "pm_sort", "pm_energy", "pm_kinetic_split",
             "pm_density_rms_diff", "pm_power_spectrum", "pm_spline_density",
-            "pm_spline_qforce", "pm_spline_step", "pm_timing_enable", "pm_timing_read",
+            "pm_spline_qforce", "pm_spline_step", "pm_spline_energy", "pm_timing_enable", "pm_timing_read",
             "pm_batch_workspace_bytes", "pm_batch_init", "pm_batch_slot_offset",
             "pm_batch_set_slot", "pm_batch_step", "pm_batch_destroy", "pm_destroy",
             "pm_strerror")
@@ -107,6 +107,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "pm_spline_qforce": ([c_void_p, c_void_p, c_void_p, c_double, c_void_p], c_int32),
         "pm_spline_step": ([c_void_p, c_void_p, c_void_p, P(c_double), c_int32, c_double],
                            c_int32),
+        "pm_spline_energy": ([c_void_p, c_void_p, c_void_p, c_double, c_double, P(PMEnergies)],
+                             c_int32),
         "pm_timing_enable": ([c_void_p, c_int32], c_int32),
         "pm_timing_read": ([c_void_p, P(PMKernelTime), c_int32, P(c_int32)], c_int32),
         "pm_batch_workspace_bytes": ([P(PMParams), c_int32, P(c_size_t)], c_int32),
@@ -248,6 +250,13 @@ def pm_spline_step(ctx: int, pos_ptr: int, vel_ptr: int, times, h: float) -> Non
                                          arr, len(t) - 1, float(h)), "pm_spline_step")
 
 
+def pm_spline_energy(ctx: int, pos_ptr: int, vel_ptr: int, h: float, a: float) -> dict:
+    out = PMEnergies()
+    _check(load_library().pm_spline_energy(c_void_p(ctx), c_void_p(pos_ptr), c_void_p(vel_ptr),
+                                           float(h), float(a), byref(out)), "pm_spline_energy")
+    return {"K": out.K, "W": out.W, "U": out.U, "E": out.E}
+
+
 def pm_timing_enable(ctx: int, on: bool) -> None:
     _check(load_library().pm_timing_enable(c_void_p(ctx), int(bool(on))), "pm_timing_enable")
 
@@ -370,6 +379,9 @@ class PMContext:
         if len(times) < 2 or any(not math.isfinite(float(t)) for t in times):
             raise ValueError("times: need at least two finite values")
         pm_spline_step(self.ctx, self._pos(pos), self._vec(vel, "vel"), times, h)
+
+    def spline_energy(self, pos, vel, a=1.0, h=3.5):
+        return pm_spline_energy(self.ctx, self._pos(pos), self._vec(vel, "vel"), h, a)
 
     def timing(self, on: bool):
         pm_timing_enable(self.ctx, on)

@@ -1007,6 +1007,41 @@ pm_status pm_spline_step(pm_ctx* c, void* d_pos, float* d_vel, const double* tim
   return PM_OK;
 }
 
+pm_status pm_spline_energy(pm_ctx* c, const void* d_pos, const float* d_vel, double h,
+                           double a, pm_energies* out) {
+  if (!c || !d_pos || !d_vel || !out) return PM_EINVAL;
+  if (!spline_h_ok(c, h)) return PM_EINVAL;
+  if (!(a > 0.0) || !isfinite(a)) return PM_EINVAL;
+  if (!c->p.comoving && a != 1.0) return PM_EINVAL;
+  const float mpm = (float)((double)c->ncell / (double)c->np);
+  PM_TRY(timed(c, kcSpline, [&] {
+    return launch_spline_deposit(c->fixed, c->logn, d_pos, c->np, (float)h, mpm,
+                                 c->sorted ? &c->tmap : nullptr, c->delta, c->stream);
+  }));
+  PM_TRY(run_poisson(c, kSrcDelta, c->delta));
+  PM_TRY(run_qpot(c, c->delta, false, kOutEnergy));
+  PM_TRY(timed(c, kcReduce, [&] {
+    return launch_reduce(c->partials, c->q_blocks, 2, c->result, c->stream);
+  }));
+  double* kp = c->partials + 2 * (size_t)c->q_blocks;
+  PM_TRY(timed(c, kcKinetic, [&] {
+    return launch_kinetic(d_vel, c->np, kp, c->k_blocks, c->stream);
+  }));
+  PM_TRY(timed(c, kcReduce, [&] {
+    return launch_reduce(kp, c->k_blocks, 1, c->result + 2, c->stream);
+  }));
+  double host[3];
+  PM_TRY(dev(hipMemcpyAsync(host, c->result, sizeof(host), hipMemcpyDeviceToHost, c->stream)));
+  PM_TRY(diag_done(c));
+  PM_TRY(dev(hipStreamSynchronize(c->stream)));
+  const double mp = (double)c->ncell / (double)c->np;
+  out->K = 0.5 * mp * host[2] / (a * a);
+  out->W = 0.5 * host[0] / a;
+  out->U = 0.5 * c->hm * c->hm * host[1] / (a * a);
+  out->E = out->K + out->W + out->U;
+  return PM_OK;
+}
+
 pm_status pm_timing_enable(pm_ctx* c, int32_t on) {
   if (!c) return PM_EINVAL;
   Timer& t = c->timer;

@@ -125,6 +125,7 @@ def test_null_context_calls(lib):
     assert lib.pm_spline_density(None, None, 3.5, None) == _lib.PM_EINVAL
     assert lib.pm_spline_qforce(None, None, None, 3.5, None) == _lib.PM_EINVAL
     assert lib.pm_spline_step(None, None, None, ctypes.byref(d), 1, 3.5) == _lib.PM_EINVAL
+    assert lib.pm_spline_energy(None, None, None, 3.5, 1.0, None) == _lib.PM_EINVAL
     assert lib.pm_destroy(None) == _lib.PM_EINVAL
 
 

@@ -76,3 +76,43 @@ def test_comoving_spline_steps_vs_oracle(pm, gpu, precision):
     ctx.spline_step(pos, vel, times[3:], 3.5)
     x, v = oracle.spline_run(x0, v0, op, times, 3.5)
     _compare(pos, vel, x, v, n, fp32)
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_spline_energy_vs_oracle(pm, gpu, precision):
+    n = 32
+    st = _jittered(n, 2)
+    fp32 = precision == 0
+    lp = pm.make_params(n, n ** 3, float(n), precision=precision, four_pi_G_rhobar=1.0,
+                        hbar_over_m=0.5, rho_floor=1e-6, rho_fp64_below=0.0)
+    op = oracle.Params(n=n, box=float(n), S=1.0, hbar_m=0.5, rho_floor=1e-6)
+    ctx = pm.PMContext(lp, device=gpu)
+    pos, vel = to_device(st, gpu, fp32_positions=fp32)
+    got = ctx.spline_energy(pos, vel, 1.0, 3.5)
+    ref = oracle.spline_energies(positions_cells(pos, n, fp32),
+                                 vel.cpu().numpy().T.astype(np.float64), op, 3.5)
+    for key in ("K", "W", "U"):
+        assert abs(got[key] - ref[key]) <= 1e-5 * abs(ref[key]), (key, got[key], ref[key])
+
+
+def test_spline_step_conserves_the_discrete_energy(pm, gpu):
+    # Sec. II A: with gravity off the kernel-gradient force conserves K + U of
+    # the spline density by construction; the leapfrog's error falls as dt^2
+    import torch
+    n = 16
+    st = _jittered(n, 6, sigma=0.25)
+    lp = pm.make_params(n, n ** 3, float(n), precision=1, four_pi_G_rhobar=0.0,
+                        hbar_over_m=0.8, rho_floor=1e-6, rho_fp64_below=0.0)
+    errs = []
+    for steps in (4, 8):
+        ctx = pm.PMContext(lp, device=gpu)
+        pos, vel = to_device(st, gpu)
+        vel.zero_()
+        e0 = ctx.spline_energy(pos, vel, 1.0, 3.5)["E"]
+        ctx.spline_step(pos, vel, list(np.linspace(0.0, 1.2, steps + 1)), 3.5)
+        e1 = ctx.spline_energy(pos, vel, 1.0, 3.5)
+        errs.append(abs(e1["E"] - e0) / e0)
+        assert e1["K"] > 0.05 * e0
+        torch.cuda.synchronize()
+    assert errs[1] < 1e-3
+    assert 3.0 < errs[0] / errs[1] < 5.5, errs

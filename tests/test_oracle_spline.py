@@ -127,3 +127,23 @@ def test_s6_spline_leapfrog_conserves_the_discrete_energy():
     # the run converts a sizeable part of K_rho into motion
     assert 0.5 * mp * float(np.sum(vv * vv)) > 0.05 * e0
     assert 3.0 < errs[0] / errs[1] < 5.5, errs
+
+
+def test_s7_spline_energies_terms():
+    # U is the K_rho whose particle gradient the force is (pinned above); W
+    # vanishes without gravity and equals the CIC form's expression on the
+    # spline density; K is Eq. (8)
+    n = 16
+    rng = np.random.default_rng(7)
+    pos = rng.random((3000, 3)) * n
+    vel = rng.standard_normal((3000, 3))
+    p0 = Params(n=n, box=float(n), S=0.0, hbar_m=0.6)
+    e = oracle.spline_energies(pos, vel, p0, 3.5)
+    assert e["W"] == 0.0
+    assert np.isclose(e["U"], oracle.spline_kinetic_rho(pos, p0, 3.5), rtol=1e-13)
+    assert np.isclose(e["K"], 0.5 * (n ** 3 / 3000) * np.sum(vel * vel), rtol=1e-13)
+    p1 = Params(n=n, box=float(n), S=1.0, hbar_m=0.6)
+    e1 = oracle.spline_energies(pos, vel, p1, 3.5, a=1.0)
+    delta = oracle.spline_deposit(pos, p1, 3.5) - 1.0
+    assert e1["W"] < 0.0
+    assert np.isclose(e1["W"], 0.5 * np.sum(delta * oracle.poisson(delta, p1)), rtol=1e-12)
