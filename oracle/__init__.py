@@ -29,6 +29,7 @@ from .pm import (  # noqa: F401
     kdk_step,
     run,
     energies,
+    gradient_energy,
     kinetic_split,
     density_rms_diff,
     layzer_irvine_error,

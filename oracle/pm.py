@@ -317,6 +317,20 @@ def energies(pos, vel, p: Params, a: float = 1.0) -> dict:
     rho, delta, phi, _ = fields(pos, p)
     kin = 0.5 * mp * float(np.sum(vel * vel)) / a ** 2
     wg = 0.5 * float(np.sum(delta * phi)) * p.dx ** 3 / a
+    u_f, u_c = gradient_energy(rho, p, a)
+    return {"K": kin, "W": wg, "U": u_f, "U_central": u_c, "E": kin + wg + u_f}
+
+
+def gradient_energy(rho, p: Params, a: float = 1.0):
+    """(forward, central) discretisations of K_rho, Eq. (6), on the mesh
+    density rho (units of the mean), with the 1/a^2 of Eq. (18).
+
+    central: Eq. (11) as printed, (hbar^2/2m^2) (dx/4) sum_j sum_d
+    (s_{j+e_d} - s_{j-e_d})^2; forward: (hbar^2/2m^2) dx sum_j sum_d
+    (s_{j+e_d} - s_j)^2, whose variation with respect to rho_j is the
+    7-point Q.  s = sqrt(max(rho, floor)); the volume element dx^3 and the
+    1/dx^2 of the squared difference quotient leave one power of dx.
+    """
     s = np.sqrt(np.maximum(rho, p.rho_floor))
     fwd = 0.0
     cen = 0.0
@@ -324,9 +338,7 @@ def energies(pos, vel, p: Params, a: float = 1.0) -> dict:
         fwd += float(np.sum((np.roll(s, -1, axis=ax) - s) ** 2))
         cen += float(np.sum((np.roll(s, -1, axis=ax) - np.roll(s, 1, axis=ax)) ** 2))
     pref = p.hbar_m ** 2 / 2.0 / a ** 2
-    u_f = pref * p.dx * fwd
-    u_c = pref * (p.dx / 4.0) * cen
-    return {"K": kin, "W": wg, "U": u_f, "U_central": u_c, "E": kin + wg + u_f}
+    return pref * p.dx * fwd, pref * (p.dx / 4.0) * cen
 
 
 def layzer_irvine_error(a_values, series):

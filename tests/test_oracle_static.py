@@ -524,6 +524,43 @@ def test_p20_static_energy_conservation_second_order(hbar_m, total_time, amp):
     assert 3.3 < e16 / e32 < 4.8, (e16, e32)
 
 
+@pytest.mark.parametrize("m,axis,n", [(1, 0, 16), (3, 1, 16), (5, 2, 32)])
+def test_gradient_energy_sine_closed_forms(m, axis, n):
+    """K_rho of Eq. (6) on sqrt(rho) = 1 + B sin(theta j), theta = 2 pi m / n
+    along one axis.  Differences: forward 2B cos(theta (j + 1/2)) sin(theta/2),
+    central (stride two, Eq. (11)) 2B cos(theta j) sin(theta); squared and
+    summed over the axis each gives N/2 times the squared amplitude, the other
+    two axes N^2.  Hence, with pref = (hbar/m)^2 / 2 and the a^-2 of Eq. (18):
+      forward  = pref dx N^3 2 B^2 sin^2(theta/2)
+      central  = pref (dx/4) N^3 2 B^2 sin^2(theta) = pref dx N^3 B^2 sin^2(theta) / 2
+    and both tend to the continuum pref B^2 k^2 L^3 / 2 (k = theta/dx) as
+    theta -> 0.  A wrong prefactor (dx instead of dx/4), stride or power of a
+    fails these."""
+    box, hm, a, B = 3.0, 0.7, 0.4, 0.05
+    p = Params(n=n, box=box, S=1.0, hbar_m=hm)
+    dx = box / n
+    j = np.arange(n)
+    th = 2 * np.pi * m / n
+    s1 = 1.0 + B * np.sin(th * j)
+    shape = [1, 1, 1]
+    shape[axis] = n
+    rho = np.broadcast_to((s1 ** 2).reshape(shape), (n, n, n)).copy()
+    fwd, cen = oracle.gradient_energy(rho, p, a)
+    pref = hm ** 2 / 2.0 / a ** 2
+    assert math.isclose(fwd, pref * dx * n ** 3 * 2 * B ** 2 * math.sin(th / 2) ** 2,
+                        rel_tol=1e-12)
+    assert math.isclose(cen, pref * dx * n ** 3 * B ** 2 * math.sin(th) ** 2 / 2, rel_tol=1e-12)
+    cont = pref * B ** 2 * (th / dx) ** 2 * box ** 3 / 2
+    # both are second-order accurate: relative errors th^2/12 (forward) and th^2/3 (central)
+    assert abs(fwd / cont - 1) < th ** 2 / 12 * 1.01
+    assert abs(cen / cont - 1) < th ** 2 / 3 * 1.01
+    # energies() reports the same two numbers for a particle state
+    st = sine_mode_state(n, m, 0.02, axis=axis)
+    e = oracle.energies(st.pos * dx, st.vel * dx, p, a)
+    f2, c2 = oracle.gradient_energy(oracle.deposit(st.pos * dx, p), p, a)
+    assert e["U"] == f2 and e["U_central"] == c2
+
+
 def test_cic_fd_scheme_grid_instability_off_half_lattice():
     """Property of the mesh-gradient scheme (not of the paper's kernel form):
     a lattice at half-cell offset is linearly stable under quantum pressure
