@@ -79,12 +79,15 @@ EVOLVE_DLNA = math.log(100.0) / 150.0
 def run_gpu(st, n, steps, warmup, a_start, kernel_pass=True, sort_every=10, fp32=False,
             evolve_to=None, box=10.0, diag=False):
     """Time `steps` steps (after `warmup`) from a_start; with evolve_to, the
-    state is first stepped (untimed) from a_start to evolve_to in steps of
-    d ln a = ln(100)/150."""
+    state is first stepped (untimed) from a_start to evolve_to under the
+    time-step condition of Sec. II A (no particle moves more than one cell
+    per step; quantum-pressure bound; d ln a at most ln(100)/150), and the
+    timed steps follow the same condition (d ln a at most ln(100)/500)."""
     import numpy as np
     import torch
 
     import paper_1608_00802_amd as pm
+    from paper_1608_00802_amd.evolve import evolve, plan
     from synth import comoving_code_params
 
     dev = torch.device("cuda:0")
@@ -103,15 +106,19 @@ def run_gpu(st, n, steps, warmup, a_start, kernel_pass=True, sort_every=10, fp32
     else:
         sort_flag = pm.PM_SORT_EVERY(sort_every) if sort_every else 0
     flags0 = 0
+    evolve_steps = 0
+    total = warmup + steps + (steps if kernel_pass else 0)
+    hm_cells = comoving_code_params(box, n, 1e-22, 0.7)["hbar_m_cells"]
     if evolve_to is not None:
-        k = max(1, int(round(math.log(evolve_to / a_start) / EVOLVE_DLNA)))
-        ev = [a_start * math.exp(i * math.log(evolve_to / a_start) / k) for i in range(k + 1)]
-        ctx.step(pos, vel, ev, flags=sort_flag)
+        ev = evolve(ctx, pos, vel, a_start, evolve_to, hm_cells, 0.3, flags=sort_flag,
+                    dlna_max=EVOLVE_DLNA)
+        evolve_steps = len(ev) - 1
         a_start = ev[-1]
         flags0 = pm.PM_CONTINUE
-    evolve_steps = len(ev) - 1 if evolve_to is not None else 0
-    total = warmup + steps + (steps if kernel_pass else 0)
-    times = [a_start * math.exp(i * DLNA) for i in range(total + 1)]
+        vmax = 2.0 * float(vel.abs().max().item())
+        times = plan(a_start, total, hm_cells, vmax, 0.3, dlna_max=DLNA)
+    else:
+        times = [a_start * math.exp(i * DLNA) for i in range(total + 1)]
     torch.cuda.synchronize()
     ctx.step(pos, vel, times[: warmup + 1], flags=sort_flag | flags0)
     torch.cuda.synchronize()
@@ -126,7 +133,7 @@ def run_gpu(st, n, steps, warmup, a_start, kernel_pass=True, sort_every=10, fp32
     wall = time.perf_counter() - t0
     ev_ms = ev0.elapsed_time(ev1)
     out = {"wall_s": wall, "event_ms": ev_ms, "np": st.npart, "evolve_steps": evolve_steps,
-           "a_timed": a_start}
+           "a_timed": a_start, "a_timed_end": times[warmup + steps]}
     if kernel_pass:
         ctx.timing(True)
         ctx.step(pos, vel, times[warmup + steps: warmup + 2 * steps + 1],
@@ -306,8 +313,49 @@ def kernel_table(kern, n, npart, steps):
     return rows
 
 
-def cpu_baseline(st, n, box):
-    """FP64 oracle, one steady-state kick-drift-kick step on the full workload."""
+def gpu_fields(st, n, box, fp32):
+    """delta, phi, Q_c and the acceleration of the initial state (a = 0.01)
+    through the library in one precision, as float64 host arrays (outside
+    every timed region)."""
+    import numpy as np
+    import torch
+
+    import paper_1608_00802_amd as pm
+    from synth import comoving_code_params
+
+    dev = torch.device("cuda:0")
+    hm = comoving_code_params(box, n, 1e-22, 0.7)["hbar_m_cells"] * (box / n) ** 2
+    lp = pm.make_params(n, st.npart, box, precision=pm.PM_FP32 if fp32 else pm.PM_FIXED32,
+                        comoving=True, omega_m=0.3, omega_l=0.7, h0=1.0, hbar_over_m=hm,
+                        rho_floor=1e-6, rho_fp64_below=1e-3)
+    ctx = pm.PMContext(lp, device=dev)
+    pos = torch.from_numpy((st.pos_f32 if fp32 else st.pos_fixed.view(np.int32)).copy()).to(dev)
+    d = torch.empty(n ** 3, dtype=torch.float32, device=dev)
+    ph = torch.empty_like(d)
+    qq = torch.empty_like(d)
+    acc = torch.empty((3, st.npart), dtype=torch.float32, device=dev)
+    ctx.deposit(pos, d)
+    ctx.poisson(None, ph)
+    ctx.qpot(None, qq)
+    ctx.force(pos, acc, 0.01)
+    torch.cuda.synchronize()
+    out = {"delta": d.cpu().numpy().astype(np.float64).reshape(n, n, n),
+           "phi": ph.cpu().numpy().astype(np.float64).reshape(n, n, n),
+           "Q": qq.cpu().numpy().astype(np.float64).reshape(n, n, n),
+           "force": acc.cpu().numpy().T.astype(np.float64)}
+    ctx.close()
+    del pos, d, ph, qq, acc
+    return out
+
+
+def cpu_baseline(st, n, box, gpu_sets=None):
+    """FP64 oracle, one steady-state kick-drift-kick step on the full workload.
+
+    The oracle's fields and forces at the initial state, computed on the way
+    (untimed), also give the relative L2 error of each precision form of the
+    library (gpu_sets: {form: gpu_fields(...)}) on rho, phi, Q and the force."""
+    import numpy as np
+
     import oracle
     from synth import comoving_code_params
     hm = comoving_code_params(box, n, 1e-22, 0.7)["hbar_m_cells"]
@@ -315,19 +363,35 @@ def cpu_baseline(st, n, box):
                       omega_m=0.3, omega_l=0.7, h0=1.0, rho_floor=1e-6)
     a0 = 0.01
     a1 = a0 * math.exp(DLNA)
-    acc0 = oracle.forces(st.pos, p)            # opening forces, untimed
+    # opening forces, untimed
+    rho, delta, phi, q = oracle.fields(st.pos, p)
+    gphi = oracle.interp_cic(oracle.grad_central(phi, p), st.pos, p)
+    gq = oracle.interp_cic(oracle.grad_central(q, p), st.pos, p)
+    errors = {}
+
+    def rel(a, b):
+        return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+    for form, g in (gpu_sets or {}).items():
+        errors[form] = {"rho": rel(1.0 + g["delta"], rho), "phi": rel(g["phi"], phi),
+                        "Q": rel(g["Q"], q),
+                        "force": rel(g["force"], gphi / a0 + gq / a0 ** 2)}
+    del rho, delta, phi, q
     t0 = time.perf_counter()
-    oracle.kdk_step(st.pos, st.vel, p, a0, a1, acc0)
+    oracle.kdk_step(st.pos, st.vel, p, a0, a1, (gphi, gq))
     dt = time.perf_counter() - t0
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:  # pragma: no cover
         cores = os.cpu_count()
-    return {"value": st.npart / dt, "unit": "particle-updates/s", "cores": 1,
-            "cores_available": cores, "kind": "oracle",
-            "sample": f"one steady-state KDK step (force evaluation at the drifted positions, "
-                      f"both half-kicks, drift) of the FP64 NumPy oracle on the full {n}^3 "
-                      f"workload, single-threaded NumPy; {dt:.1f} s"}
+    out = {"value": st.npart / dt, "unit": "particle-updates/s", "cores": 1,
+           "cores_available": cores, "kind": "oracle",
+           "sample": f"one steady-state KDK step (force evaluation at the drifted positions, "
+                     f"both half-kicks, drift) of the FP64 NumPy oracle on the full {n}^3 "
+                     f"workload, single-threaded NumPy; {dt:.1f} s"}
+    if errors:
+        out["gpu_rel_l2_at_a0"] = errors
+    return out
 
 
 def serve_section(trace, ics):
@@ -442,18 +506,20 @@ def main():
                      sort_every=args.sort_every, fp32=True, box=args.box)
         vf = rf["np"] * args.steps / rf["wall_s"]
         line["plain_fp32"] = {
-            "form": "float32 positions, float atomics deposit, same FFT/stencil/gather kernels",
+            "form": "float32 positions, float atomics deposit, sqrt(rho) formed directly for Q, "
+                    "same FFT/stencil/gather kernels",
             "value": vf, "ms_per_step": rf["wall_s"] * 1e3 / args.steps,
-            "speedup_fixed_vs_fp32": round(value / vf, 3),
-            "accuracy": "both forms meet the same one-step oracle tolerance "
-                        "(rel-L2 < 1e-5 on rho, phi, Q; tests/test_gpu_parity.py)"}
+            "speedup_fixed_vs_fp32": round(value / vf, 3)}
     if not args.no_evolved:
         re_ = run_gpu(st, n, args.steps, args.warmup, 0.01, kernel_pass=not args.no_kernel_pass,
                       sort_every=args.sort_every, evolve_to=0.5, box=args.box,
                       diag=not args.no_diag)
         line["evolved"] = {
-            "state": f"the same box stepped from a = 0.01 to a = 0.5 "
-                     f"({re_['evolve_steps']} steps, untimed), then timed: nonlinear, clustered",
+            "state": f"the same box stepped from a = 0.01 to a = 0.5 ({re_['evolve_steps']} "
+                     f"steps, untimed) under the time-step condition of Sec. II A (no particle "
+                     f"moves more than one cell per step, quantum-pressure bound, d ln a <= "
+                     f"ln(100)/150), then timed from a = {re_['a_timed']:.4f} to "
+                     f"{re_['a_timed_end']:.4f} under the same condition: nonlinear, clustered",
             "value": re_["np"] * args.steps / re_["wall_s"],
             "ms_per_step": re_["wall_s"] * 1e3 / args.steps,
             "finite": re_["finite"],
@@ -468,7 +534,24 @@ def main():
         line["serving"] = serve_section(trace, ics)
         del ics
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(st, n, args.box)
+        sets = {"fixed": gpu_fields(st, n, args.box, False)}
+        if not args.no_fp32:
+            sets["plain_fp32"] = gpu_fields(st, n, args.box, True)
+        line["cpu_baseline"] = cpu_baseline(st, n, args.box, sets)
+        del sets
+        errs = line["cpu_baseline"].get("gpu_rel_l2_at_a0", {})
+        if "plain_fp32" in line and "plain_fp32" in errs:
+            # the speedup counts as one at equal accuracy only where the plain
+            # form meets the same 1e-5 bound on every field
+            worst = max(errs["plain_fp32"].values())
+            line["plain_fp32"]["rel_l2_vs_oracle_at_a0"] = errs["plain_fp32"]
+            line["plain_fp32"]["fixed_rel_l2_vs_oracle_at_a0"] = errs["fixed"]
+            line["plain_fp32"]["equal_accuracy"] = bool(worst < 1e-5)
+            if worst >= 1e-5:
+                line["plain_fp32"]["note"] = (
+                    "unequal accuracy: the plain FP32 form misses the 1e-5 bound that the "
+                    "fixed-point form meets, so the speedup compares a more accurate step "
+                    "with a less accurate one")
     line["finite"] = res["finite"]
     print(json.dumps(line), flush=True)
 

@@ -4,11 +4,14 @@
 // Fixed-point form: positions are uint32 u*2^32/N, so the top log2(N) bits are
 // the cell index and the low B = 32 - log2(N) bits the fraction.  Each particle
 // carries exactly 2^40 integer mass units.  A corner weight is
-// w_x w_y w_z / 2^(3B) of the particle: the product w_x w_y (< 2^51) is exact
-// in 64-bit integers and in FP64, the multiplication by w_z is one FP64
-// rounding (relative 2^-53), the scale to 2^40 units is an exact power of two
-// and rint gives the integer weight -- deterministic, within 0.5 + 2^-10 units
-// of the exact value.  The corner with the largest weight takes the remainder,
+// w_x w_y w_z / 2^(3B) of the particle: the product w_x w_y (< 2^(2B)) is
+// exact in 64-bit integers, and exact in FP64 for N >= 64 (2B <= 52); the
+// multiplication by w_z is one FP64 rounding (relative 2^-53 of a value of at
+// most 2^40 units: at most 2^-13 units), the scale to 2^40 units is an exact
+// power of two and rint gives the integer weight -- deterministic, within
+// 0.5 + 2^-13 units of the exact value.  For N <= 32 (B >= 27) w_x w_y reaches
+// 2^(2B) >= 2^54 and its conversion to FP64 is a second rounding of the same
+// size: within 0.5 + 2^-12 units.  The corner with the largest weight takes the remainder,
 // so every particle deposits exactly 2^40 units.  Integer atomics commute,
 // which makes the mesh bitwise independent of particle order and scheduling.
 //

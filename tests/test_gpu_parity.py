@@ -107,7 +107,7 @@ def test_poisson_sine_closed_form(pm, gpu, n):
     assert rel_l2(phi.cpu().numpy().reshape(n, n, n), expect) < 2e-6
 
 
-@pytest.mark.parametrize("n", [16, 32, 64, 128, 256])
+@pytest.mark.parametrize("n", [16, 32, 64, 128, 256, 512])
 def test_poisson_random_vs_oracle(pm, gpu, n):
     import torch
     rng = np.random.default_rng(100 + n)
@@ -265,6 +265,12 @@ def test_single_mode_drift_100_steps(pm, gpu, precision):
     amp0 = periodic_diff(x0[:, 0], q[:, 0], 32) @ basis / (basis @ basis)
     if precision == 1:
         assert abs(amp / amp0 - 1.486711) < 1e-4
+    else:
+        # the plain FP32 form: 1.1e-5 cell of drift measured (inside the 1e-4
+        # budget), the growth 2.3e-3 below linear theory (the 1e-3-cell mode is
+        # resolved to ~1e-6 cell by FP32 positions near 16 cells)
+        assert drift < 5e-5, drift
+        assert abs(amp / amp0 - 1.486711) < 5e-3
     print(f"single mode precision={precision}: drift vs oracle {drift:.3e} cell, growth {amp / amp0:.7f}")
 
 
