@@ -30,8 +30,9 @@
  * Workspace contents.  Bytes [0, 8 N^3) of the workspace hold the deposited
  *   mass mesh after pm_deposit, pm_step or pm_energy: int64 in units of 2^-40
  *   particle masses (PM_FIXED32; exactly 2^40 per particle in total) or float
- *   sums of CIC weights (PM_FP32, first 4 N^3 bytes).  Everything else in the
- *   workspace is private.
+ *   sums of CIC weights (PM_FP32, first 4 N^3 bytes); after pm_spline_density,
+ *   pm_spline_step or pm_spline_energy, the int64 spline density in the same
+ *   units (both precisions).  Everything else in the workspace is private.
  * Asynchrony.  All calls except pm_workspace_bytes, pm_energy,
  *   pm_kinetic_split, pm_density_rms_diff, pm_power_spectrum, pm_spline_energy
  *   and pm_destroy only enqueue work on the context's HIP stream and return.  Argument errors
@@ -145,9 +146,12 @@ pm_status pm_init(const pm_params* params, void* d_workspace, size_t bytes,
  * not NULL, delta (float [N^3]) is also written there. */
 pm_status pm_deposit(pm_ctx* ctx, const void* d_pos, float* d_delta);
 
-/* Gravity: phi with lap(phi) = S delta, S = four_pi_G_rhobar (static) or
- * 1.5 omega_m h0^2 (comoving, the a-independent potential phi_c), through
- * the FFT with the Green's function of the 7-point Laplacian, zero mean.
+/* Gravity (Sec. II A, Eq. (2): the Poisson equation of the potential V,
+ * solved on the mesh that carries the density of step (i)): phi with
+ * lap(phi) = S delta, S = four_pi_G_rhobar (static) or 1.5 omega_m h0^2
+ * (comoving, the a-independent potential phi_c of Sec. III), through the FFT
+ * with the Green's function of the 7-point Laplacian, zero mean (the k = 0
+ * mode of a periodic box carries no force).
  * d_delta NULL uses the context's delta from pm_deposit.  The result stays
  * in the context (for pm_force and pm_step) and is also written to d_phi
  * (float [N^3]) if not NULL. */
@@ -168,7 +172,10 @@ pm_status pm_qpot(pm_ctx* ctx, const float* d_delta, float* d_q);
 pm_status pm_force(pm_ctx* ctx, const float* d_phi, const float* d_q,
                    const void* d_pos, float* d_acc, double a);
 
-/* Kick-drift-kick leapfrog over the schedule times[0..nsteps] (host array:
+/* The leapfrog of Sec. II A with the quantum force added to gravity
+ * (principal steps (i)-(iii) at every force evaluation; comoving form with
+ * the 1/a^2 of Q from Eq. (18), Sec. III).  Kick-drift-kick over the
+ * schedule times[0..nsteps] (host array:
  * times in a static box, scale factors in a comoving box, strictly
  * increasing).  Positions and velocities are synchronised on entry and on
  * return; kicks between steps are merged, so each step costs one deposit,
@@ -180,6 +187,23 @@ pm_status pm_force(pm_ctx* ctx, const float* d_phi, const float* d_q,
 pm_status pm_step(pm_ctx* ctx, void* d_pos, float* d_vel, const double* times,
                   int32_t nsteps, int32_t flags);
 
+/* pm_step that also records the energies of Sec. II A and II B (as
+ * pm_energy: K of Eq. (8), W = W_g, U = K_rho of Eq. (6) by the forward
+ * differences of Eq. (11)'s mesh sum, E = K + W + U) at every synchronised
+ * time of the call.  d_energies: device array of (nsteps + 1) x 4 doubles;
+ * row s receives K, W, U, E at times[s] (a = times[s] in a comoving box).
+ * The partial sums are formed inside the step's own kernels: the Q stencil
+ * adds up delta phi and the squared forward differences per block, the fused
+ * gather splits each merged kick at the synchronised time and adds up |p|^2
+ * there; a one-block kernel per row sums the partials in a fixed order, so
+ * the rows are deterministic.  With PM_CONTINUE on a context whose fields
+ * are those of the positions, row 0 is left untouched (it is the last row of
+ * the previous call).  Enqueues only.  The trajectory equals pm_step's up to
+ * the rounding of the split kick (closing and opening halves added one after
+ * the other instead of as one merged factor). */
+pm_status pm_step_energies(pm_ctx* ctx, void* d_pos, float* d_vel, const double* times,
+                           int32_t nsteps, int32_t flags, double* d_energies);
+
 /* Reorder the particles in place by mesh tile (8 x 8 x 32 cells; counting
  * sort, order inside a tile unspecified) and remember the tile ranges.
  * Afterwards the deposit and the gather stage each tile's mesh window in
@@ -190,8 +214,12 @@ pm_status pm_step(pm_ctx* ctx, void* d_pos, float* d_vel, const double* times,
  * Call again every few steps as particles move. */
 pm_status pm_sort(pm_ctx* ctx, void* d_pos, float* d_vel, int32_t* d_ids);
 
-/* K, W, U, E of the synchronised state (d_pos, d_vel) at scale factor a
- * (1 in a static box).  Recomputes delta and phi; blocks until done.
+/* The energies of Sec. II A and II B for the synchronised state (d_pos,
+ * d_vel) at scale factor a (1 in a static box): K = K_v of Eq. (8), U = K_rho
+ * of Eq. (6) discretised on the mesh as in Eq. (11) (forward differences, the
+ * exact conjugate of the 7-point Laplacian in Q), W = W_g the gravitational
+ * potential energy (the energy of Eq. (16)'s scale symmetry); definitions
+ * and units at pm_energies.  Recomputes delta and phi; blocks until done.
  * Leaves the context's delta, phi and Q at d_pos. */
 pm_status pm_energy(pm_ctx* ctx, const void* d_pos, const float* d_vel,
                     double a, pm_energies* out);
@@ -250,9 +278,14 @@ pm_status pm_power_spectrum(pm_ctx* ctx, const void* d_pos, int32_t nbins,
  * pm_spline_density: d_delta (float [N^3], caller-owned) receives
  * rho/rho_bar - 1 at the mesh nodes from Eq. (9) with the cubic spline of
  * Eq. (15), smoothing length h in cells (the paper uses 3.5 to 4):
- * rho(x_j) = sum_i m W(|x_j - q_i|, h), m = N^3 / Np mean densities.  FP32
- * atomic sums (last bits vary from run to run).  Pass the result to pm_qpot
- * for Q on the nodes.
+ * rho(x_j) = sum_i m W(|x_j - q_i|, h), m = N^3 / Np mean densities.  Each
+ * kernel value is rounded once to 2^-40 of a particle mass and summed as a
+ * 64-bit integer into the workspace's mass mesh (bytes [0, 8 N^3), the
+ * units of the fixed-point CIC deposit, in both precisions): the sums are
+ * bitwise reproducible and independent of particle order, and delta is
+ * formed by the exact subtraction of the mean.  The context's delta is the
+ * spline density's afterwards: pm_qpot(ctx, NULL, d_q) gives Q on it, with
+ * the FP64 path below rho_fp64_below in the fixed-point form.
  *
  * pm_spline_qforce: d_acc ([3][Np] float) receives the quantum acceleration of
  * every particle by the kernel gradient, Eq. (14): a_i = sum_j Q_j
@@ -261,7 +294,9 @@ pm_status pm_power_spectrum(pm_ctx* ctx, const void* d_pos, int32_t nbins,
  * Eq. (11) whose node derivative is Q.  d_q is float [N^3] as from pm_qpot.
  *
  * Both enqueue only.  PM_EINVAL for null pointers or h outside
- * [0.5, 16] or so wide that 2 floor(h) + 2 > N. */
+ * [2, 16] (below two cells the lattice sum of W, a particle's deposited
+ * mass, varies with its position by more than 0.2 %) or so wide that
+ * 2 floor(h) + 2 > N. */
 pm_status pm_spline_density(pm_ctx* ctx, const void* d_pos, double h, float* d_delta);
 pm_status pm_spline_qforce(pm_ctx* ctx, const void* d_pos, const float* d_q, double h,
                            float* d_acc);
@@ -270,12 +305,16 @@ pm_status pm_spline_qforce(pm_ctx* ctx, const void* d_pos, const float* d_q, dou
  * paper's own coupling (Sec. II A): every force evaluation deposits the
  * spline density (pm_spline_density), solves gravity on it (FFT Poisson,
  * -grad phi interpolated by cloud-in-cell, as the host code's PM does) and
- * takes Q on it with the kernel-gradient force (pm_spline_qforce).  Comoving
- * factors as pm_step (Q's kick carries 1/a^3, gravity's 1/a^2).  Unfused and
- * unsorted: no window halos, no merged half-kicks, two extra [3][Np] float
- * arrays in the workspace's particle buffers.  Enqueues only; positions and
- * velocities are synchronised on entry and on return.  Leaves no
- * cloud-in-cell field valid (later calls recompute them). */
+ * takes Q on it with the kernel-gradient force (pm_spline_qforce), with the
+ * FP64 near-empty path of the fixed-point form.  Comoving factors as pm_step
+ * (Q's kick carries 1/a^3, gravity's 1/a^2).  Unfused: separate deposit,
+ * Poisson, Q, force, kick and drift kernels, no merged half-kicks, two extra
+ * [3][Np] float arrays in the workspace's particle buffers.  The particle
+ * order is the caller's; on a context sorted by pm_sort the deposit runs
+ * from the tiles' LDS windows (particles that left their tile since the sort
+ * add directly; the result does not depend on it).  Enqueues only;
+ * positions and velocities are synchronised on entry and on return.  Leaves
+ * no cloud-in-cell field valid (later calls recompute them). */
 pm_status pm_spline_step(pm_ctx* ctx, void* d_pos, float* d_vel, const double* times,
                          int32_t nsteps, double h);
 
@@ -328,6 +367,18 @@ typedef struct {
 
 /* Largest number of steps one pm_batch_step call may take. */
 #define PM_BATCH_MAX_STEPS 256
+/* Flag of pm_batch_step: capture the call's kernels in a HIP graph the first
+ * time a call of its shape is made -- shape: the number of listed slots,
+ * nsteps, the other flags and whether every listed slot was sorted on entry
+ * -- and replay the graph for later calls of the same shape (up to 64 graphs
+ * per batch, freed by pm_batch_destroy); the upload of the call's slot list
+ * and kick/drift table precedes the graph on the stream as in an uncaptured
+ * call.
+ * The slot identities and the time-step factors are data of the uploaded
+ * table, so a replay advances whichever slots are listed along their own
+ * schedules; results equal those of the uncaptured call bitwise.  Needs a
+ * non-default stream (PM_EINVAL on the NULL stream). */
+#define PM_BATCH_GRAPH (1 << 25)
 
 /* Workspace of a batch: params as for pm_workspace_bytes (box and
  * hbar_over_m are ignored: they are per slot), slots >= 1. */
@@ -353,8 +404,8 @@ pm_status pm_batch_set_slot(pm_batch* batch, int32_t slot, const pm_slot_params*
  * schedule times[i * (nsteps + 1) .. i * (nsteps + 1) + nsteps] (host array,
  * strictly increasing; scale factors in a comoving batch).  State in and out
  * is synchronised, as for pm_step.  flags: PM_CONTINUE (every listed slot's
- * fields are those of its positions, left by the previous pm_batch_step) and
- * PM_SORT_EVERY(k).  1 <= nsteps <= PM_BATCH_MAX_STEPS. */
+ * fields are those of its positions, left by the previous pm_batch_step),
+ * PM_SORT_EVERY(k) and PM_BATCH_GRAPH.  1 <= nsteps <= PM_BATCH_MAX_STEPS. */
 pm_status pm_batch_step(pm_batch* batch, void* d_pos, float* d_vel, int32_t nactive,
                         const int32_t* slots, const double* times, int32_t nsteps,
                         int32_t flags);

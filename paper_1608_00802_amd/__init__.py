@@ -6,6 +6,7 @@ this package holds its ctypes binding, the build script and the serving loop.
 
 from ._lib import (  # noqa: F401
     EXPORTED,
+    PM_BATCH_GRAPH,
     PM_CONTINUE,
     PM_FIXED32,
     PM_FP32,
@@ -34,6 +35,7 @@ from ._lib import (  # noqa: F401
     pm_spline_step,
     pm_spline_energy,
     pm_step,
+    pm_step_energies,
     pm_timing_enable,
     pm_timing_read,
     pm_workspace_bytes,

@@ -20,13 +20,14 @@ PM_OK, PM_EINVAL, PM_ENOMEM, PM_EDEVICE, PM_EUNSUPPORTED, PM_ESTATE = 0, -1, -2,
 PM_FP32, PM_FIXED32 = 0, 1
 PM_CONTINUE = 1
 PM_SORT_AUTO = 1 << 24
+PM_BATCH_GRAPH = 1 << 25
 
 
 def PM_SORT_EVERY(k: int) -> int:
     return (int(k) & 0xffff) << 8
 
 EXPORTED = ("pm_workspace_bytes", "pm_init", "pm_deposit", "pm_poisson", "pm_qpot",
-            "pm_force", "pm_step", "pm_sort", "pm_energy", "pm_kinetic_split",
+            "pm_force", "pm_step", "pm_step_energies", "pm_sort", "pm_energy", "pm_kinetic_split",
             "pm_density_rms_diff", "pm_power_spectrum", "pm_spline_density",
             "pm_spline_qforce", "pm_spline_step", "pm_spline_energy", "pm_timing_enable", "pm_timing_read",
             "pm_batch_workspace_bytes", "pm_batch_init", "pm_batch_slot_offset",
@@ -96,6 +97,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "pm_qpot": ([c_void_p, c_void_p, c_void_p], c_int32),
         "pm_force": ([c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double], c_int32),
         "pm_step": ([c_void_p, c_void_p, c_void_p, P(c_double), c_int32, c_int32], c_int32),
+        "pm_step_energies": ([c_void_p, c_void_p, c_void_p, P(c_double), c_int32, c_int32,
+                              c_void_p], c_int32),
         "pm_sort": ([c_void_p, c_void_p, c_void_p, c_void_p], c_int32),
         "pm_energy": ([c_void_p, c_void_p, c_void_p, c_double, P(PMEnergies)], c_int32),
         "pm_kinetic_split": ([c_void_p, c_void_p, c_void_p, c_double, P(PMKineticParts)],
@@ -192,6 +195,15 @@ def pm_step(ctx: int, pos_ptr: int, vel_ptr: int, times, flags: int = 0) -> None
     arr = (c_double * len(t))(*t)
     _check(load_library().pm_step(c_void_p(ctx), c_void_p(pos_ptr), c_void_p(vel_ptr), arr,
                                   len(t) - 1, int(flags)), "pm_step")
+
+
+def pm_step_energies(ctx: int, pos_ptr: int, vel_ptr: int, times, flags: int,
+                     energies_ptr: int) -> None:
+    t = [float(v) for v in times]
+    arr = (c_double * len(t))(*t)
+    _check(load_library().pm_step_energies(c_void_p(ctx), c_void_p(pos_ptr), c_void_p(vel_ptr),
+                                           arr, len(t) - 1, int(flags), c_void_p(energies_ptr)),
+           "pm_step_energies")
 
 
 def pm_sort(ctx: int, pos_ptr: int, vel_ptr: int, ids_ptr: int | None) -> None:
@@ -345,6 +357,19 @@ class PMContext:
         if len(times) < 2 or any(not math.isfinite(float(t)) for t in times):
             raise ValueError("times: need at least two finite values")
         pm_step(self.ctx, self._pos(pos), self._vec(vel, "vel"), times, flags)
+
+    def step_energies(self, pos, vel, times, energies, flags=0):
+        """pm_step_energies; energies: float64 [len(times), 4] on the device
+        (rows K, W, U, E per synchronised time)."""
+        torch = self.torch
+        if len(times) < 2 or any(not math.isfinite(float(t)) for t in times):
+            raise ValueError("times: need at least two finite values")
+        if energies.dtype != torch.float64 or energies.device != self.device \
+                or not energies.is_contiguous() or tuple(energies.shape) != (len(times), 4):
+            raise ValueError(f"energies: need contiguous float64 [{len(times)}, 4] on "
+                             f"{self.device}")
+        pm_step_energies(self.ctx, self._pos(pos), self._vec(vel, "vel"), times, flags,
+                         energies.data_ptr())
 
     def sort(self, pos, vel, ids=None):
         torch = self.torch

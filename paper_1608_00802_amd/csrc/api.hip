@@ -4,7 +4,10 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
+#include <map>
 #include <new>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -18,13 +21,13 @@ namespace {
 enum KernelClass : int {
   kcFill, kcDeposit, kcR2C, kcFftY, kcFftX, kcFftYInv, kcC2R, kcQpot, kcGatherKD, kcKick,
   kcForce, kcReduce, kcKinetic, kcSortCount, kcSortScan, kcSortScatter, kcSortCopy,
-  kcMomentum, kcDiagNodes, kcPower, kcSpline, kcSplineForce, kcCount
+  kcMomentum, kcDiagNodes, kcPower, kcSpline, kcSplineForce, kcEnergyRow, kcCount
 };
 const char* const kKernelNames[kcCount] = {
     "fill_zero", "deposit", "r2c_z", "fft_y", "fft_x_green", "fft_y_inv", "c2r_z",
     "qpot", "gather_kick_drift", "kick", "force", "reduce", "kinetic", "sort_count",
     "sort_scan", "sort_scatter", "sort_copy", "momentum_deposit", "diag_nodes", "fft_x_power", "spline_deposit",
-    "spline_qforce"};
+    "spline_qforce", "energy_row"};
 
 struct Timer {
   bool on = false;
@@ -62,6 +65,7 @@ struct pm_ctx {
   float2* tw;
   float* s2;
   double* partials;  // energy partial sums
+  double* kpart;     // |p|^2 partial sums of the energy form of the gather
   double* result;    // reduced energies (device)
   unsigned* tile_counts;  // [kSlices][count_stride(tiles)]
   unsigned* scan_sums;    // [2 * scan_blocks(tiles)]
@@ -111,6 +115,9 @@ struct pm_batch {
   char* h_stage[2] = {nullptr, nullptr};
   hipEvent_t h_done[2] = {nullptr, nullptr};
   int h_next = 0;
+  // PM_BATCH_GRAPH: executable graphs of the kernels of captured calls, by
+  // shape (listed slots, steps, flags, every listed slot sorted on entry)
+  std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;
 };
 
 namespace {
@@ -126,8 +133,8 @@ int ilog2_exact(int n) {
 }
 
 struct Layout {
-  size_t mass, delta, phi, q, spec, tw, s2, partials, result, tile_counts, scan_sums, slice_start,
-      tile_start, chunk_start, sort_key, sort_rank, pos_tmp, vel_tmp, ids_tmp, total;
+  size_t mass, delta, phi, q, spec, tw, s2, partials, kpart, result, tile_counts, scan_sums,
+      slice_start, tile_start, chunk_start, sort_key, sort_rank, pos_tmp, vel_tmp, ids_tmp, total;
 };
 
 Layout layout_for(const pm_params& p) {
@@ -149,10 +156,13 @@ Layout layout_for(const pm_params& p) {
   L.s2 = take(4 * n);
   const size_t qb = nc / kBlock;
   L.partials = take(8 * (2 * qb + 1024));
-  L.result = take(8 * 16);
   const int logn = ilog2_exact(p.n_mesh);
   const size_t tiles = logn > 0 ? (size_t)tile_count(logn) : 1;
   const size_t np = (size_t)(p.n_part > 0 ? p.n_part : 1);
+  // one |p|^2 partial per gather block: at most 65536 blocks unsorted, one
+  // per chunk of a tile sorted
+  L.kpart = take(8 * std::max<size_t>(65536, tiles + (np + kChunk - 1) / kChunk));
+  L.result = take(8 * 16);
   L.tile_counts = take(4 * (size_t)kSlices * count_stride((int)tiles));
   L.scan_sums = take(8 * (size_t)scan_blocks((int)tiles));
   L.slice_start = take(4 * (tiles * kSlices + 1));
@@ -185,6 +195,8 @@ pm_status check_params(const pm_params* p) {
   } else {
     if (!(p->four_pi_G_rhobar >= 0.0) || !isfinite(p->four_pi_G_rhobar)) return PM_EINVAL;
   }
+  // the mean integer mass per cell 2^40 Np / N^3 (deposit units) fits int64
+  if ((double)p->n_part * ldexp(1.0, kMassShift - 3 * logn) > 4.0e18) return PM_EINVAL;
   if (p->precision == PM_FIXED32) {
     // mean integer mass per cell must be an integer: 2^40 Np / N^3
     if (3 * logn > kMassShift) return PM_EUNSUPPORTED;
@@ -380,6 +392,7 @@ size_t batch_header(int slots) {
 
 // Release a batch's host resources once its queued uploads are done.
 void batch_free(pm_batch* b) {
+  for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.second);
   for (int i = 0; i < 2; ++i) {
     if (b->h_done[i]) {
       (void)hipEventSynchronize(b->h_done[i]);
@@ -407,8 +420,11 @@ pm_status ctx_setup(pm_ctx* c, const pm_params* params, char* base, hipStream_t 
   c->has_q = c->hm > 0.0;
   c->S = params->comoving ? 1.5 * params->omega_m * params->h0 * params->h0
                           : params->four_pi_G_rhobar;
+  // mean integer mass per cell, 2^40 Np / N^3 (an integer for N <= 512): the
+  // units of the fixed-point CIC deposit and, in both precisions, of the
+  // spline deposit
   const int sh = kMassShift - 3 * c->logn;
-  const long long mbar = c->fixed ? (long long)(params->n_part) << (sh > 0 ? sh : 0) : 0;
+  const long long mbar = (long long)(params->n_part) << (sh > 0 ? sh : 0);
   c->conv.mbar = mbar;
   c->conv.dmbar = (double)mbar;
   c->conv.acc_norm = (float)((double)c->ncell / (double)c->np);
@@ -429,6 +445,7 @@ pm_status ctx_setup(pm_ctx* c, const pm_params* params, char* base, hipStream_t 
   c->tw = reinterpret_cast<float2*>(base + L.tw);
   c->s2 = reinterpret_cast<float*>(base + L.s2);
   c->partials = reinterpret_cast<double*>(base + L.partials);
+  c->kpart = reinterpret_cast<double*>(base + L.kpart);
   c->result = reinterpret_cast<double*>(base + L.result);
   c->tile_counts = reinterpret_cast<unsigned*>(base + L.tile_counts);
   c->scan_sums = reinterpret_cast<unsigned*>(base + L.scan_sums);
@@ -655,8 +672,10 @@ pm_status copy_particles(pm_ctx* c, void* pos, float* vel, const void* src_pos,
 
 }  // namespace
 
-pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int32_t nsteps,
-                  int32_t flags) {
+// The step loop of pm_step and pm_step_energies (d_en: device rows of K, W,
+// U, E per synchronised time, or null).
+static pm_status step_impl(pm_ctx* c, void* d_pos, float* d_vel, const double* times,
+                           int32_t nsteps, int32_t flags, double* d_en) {
   if (!c || !d_pos || !d_vel || !times) return PM_EINVAL;
   if (nsteps < 1) return PM_EINVAL;
   if (flags & ~(PM_CONTINUE | PM_SORT_EVERY(0xffff) | PM_SORT_AUTO)) return PM_EINVAL;
@@ -687,9 +706,27 @@ pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int
     const Kick open = kick(c->p, times[s], midpoint(c->p, times[s], times[s + 1]));
     return Kick{close.g + open.g, close.q + open.q};
   };
+  // Energy rows: the stencil at x_s leaves the (delta phi, gradient)
+  // partials, the gather of step s (or the closing half-kick) the |p|^2
+  // partials of the momentum synchronised at t_s; one small kernel per row
+  // reduces them in a fixed order.
+  const bool en = d_en != nullptr;
+  const double mp = (double)c->ncell / (double)c->np;
+  auto energy_row = [&](int s) -> pm_status {
+    const double a = c->p.comoving ? times[s] : 1.0;
+    const EnergyScale sc = {0.5 * mp / (a * a), 0.5 / a, 0.5 * c->hm * c->hm / (a * a)};
+    const int nk = (int)gather_blocks(c->np, c->sorted ? &c->tmap : nullptr);
+    return timed(c, kcEnergyRow, [&] {
+      return launch_energy_row(c->partials, c->q_blocks, c->kpart, nk, sc, d_en + 4 * (size_t)s,
+                               c->stream);
+    });
+  };
+  bool row0 = false;
   // Inside the call the fields for the next gather are written as the one
   // potential psi = F_g phi + F_q Q it needs; the fields left at the end of
   // the call stay phi and Q, for the closing half-kick and a continued call.
+  // The energy form keeps phi and Q apart (the gather splits the kick at the
+  // synchronised time).
   bool psi = false;
   if (!((flags & PM_CONTINUE) && c->fields_at_pos)) {
     // Sorting before the opening deposit lets it run from tiles: from a
@@ -698,8 +735,9 @@ pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int
     // not depend on the order.
     if (c->fixed && !c->sorted && (sort_auto || sort_every > 0)) PM_TRY(sort_step());
     const Kick k0 = merged(0, Kick{0.0, 0.0});
-    PM_TRY(run_fields(c, cur_pos, false, true, &k0));
-    psi = c->has_q;
+    PM_TRY(run_fields(c, cur_pos, en, true, en ? nullptr : &k0));
+    psi = c->has_q && !en;
+    row0 = en;
   }
   c->fields_at_pos = false;
   const double fdu = c->fixed ? ldexp(1.0, c->B) : 1.0;
@@ -715,7 +753,14 @@ pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int
       PM_TRY(sort_step());
     }
     GatherConst gc;
-    if (psi) {
+    if (en) {
+      const Kick open = kick(c->p, t0, tm);
+      gc.fg = (float)close.g;
+      gc.fq = (float)close.q;
+      gc.og = (float)open.g;
+      gc.oq = (float)open.q;
+      gc.kpart = c->kpart;
+    } else if (psi) {
       gc.fg = 1.0f;
       gc.fq = 0.0f;
       gc.psi = 1;
@@ -735,14 +780,15 @@ pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int
                            c->sorted ? &c->tmap : nullptr, c->mass, c->stream, Batch(), wide);
     }));
     ++c->since_sort;
+    if (en && (s > 0 || row0)) PM_TRY(energy_row(s));
     if (sort_auto && !c->stat_pending) PM_TRY(sample_sort_stat(c));
     close = kick(c->p, tm, t1);
-    if (s + 1 < nsteps) {
+    if (s + 1 < nsteps && !en) {
       const Kick kn = merged(s + 1, close);
       PM_TRY(run_fields(c, cur_pos, false, false, &kn));
       psi = c->has_q;
     } else {
-      PM_TRY(run_fields(c, cur_pos, false, false));
+      PM_TRY(run_fields(c, cur_pos, en, false));
       psi = false;
     }
   }
@@ -750,6 +796,7 @@ pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int
   gc.fg = (float)close.g;
   gc.fq = (float)close.q;
   gc.fd_units = 0.0;
+  if (en) gc.kpart = c->kpart;
   // closing half-kick; if the particles ended in the workspace copies, the
   // same pass writes them back to the caller's arrays
   const bool back = cur_pos != d_pos;
@@ -758,9 +805,21 @@ pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int
                          c->np, gc, c->sorted ? &c->tmap : nullptr, nullptr, c->stream, Batch(),
                          false, back ? d_pos : nullptr, back ? d_vel : nullptr);
   }));
+  if (en) PM_TRY(energy_row(nsteps));
   if (back && !c->sorted) PM_TRY(copy_particles(c, d_pos, d_vel, cur_pos, cur_vel));
   c->fields_at_pos = true;
   return PM_OK;
+}
+
+pm_status pm_step(pm_ctx* c, void* d_pos, float* d_vel, const double* times, int32_t nsteps,
+                  int32_t flags) {
+  return step_impl(c, d_pos, d_vel, times, nsteps, flags, nullptr);
+}
+
+pm_status pm_step_energies(pm_ctx* c, void* d_pos, float* d_vel, const double* times,
+                           int32_t nsteps, int32_t flags, double* d_energies) {
+  if (!d_energies) return PM_EINVAL;
+  return step_impl(c, d_pos, d_vel, times, nsteps, flags, d_energies);
 }
 
 pm_status pm_sort(pm_ctx* c, void* d_pos, float* d_vel, int32_t* d_ids) {
@@ -923,18 +982,43 @@ pm_status pm_power_spectrum(pm_ctx* c, const void* d_pos, int32_t nbins, double*
   return PM_OK;
 }
 
+// Smoothing lengths of at least two cells: below that the lattice sum of the
+// kernel of Eq. (15) drifts away from one (a particle's deposited mass varies
+// by +-9 % with its position at h = 1.5 and by +-0.2 % at h = 2), and below
+// sqrt(3)/2 cells a particle can miss every node.
 static bool spline_h_ok(const pm_ctx* c, double h) {
-  return isfinite(h) && h >= 0.5 && 2.0 * floor(h) + 2.0 <= (double)c->N && h <= 16.0;
+  return isfinite(h) && h >= 2.0 && 2.0 * floor(h) + 2.0 <= (double)c->N && h <= 16.0;
+}
+
+// The spline density of the positions into the context's mass mesh, in the
+// integer units of the CIC deposit (both precisions).
+static pm_status run_spline_density(pm_ctx* c, const void* pos, double h) {
+  PM_TRY(timed(c, kcFill, [&] {
+    return launch_fill_zero(c->mass, 8 * c->ncell + kStrayBytes, c->stream);
+  }));
+  return timed(c, kcSpline, [&] {
+    return launch_spline_deposit(c->fixed, c->logn, pos, c->np, (float)h,
+                                 c->sorted ? &c->tmap : nullptr,
+                                 static_cast<unsigned long long*>(c->mass), c->stream);
+  });
 }
 
 pm_status pm_spline_density(pm_ctx* c, const void* d_pos, double h, float* d_delta) {
   if (!c || !d_pos || !d_delta) return PM_EINVAL;
   if (!spline_h_ok(c, h)) return PM_EINVAL;
-  const float mpm = (float)((double)c->ncell / (double)c->np);
-  return timed(c, kcSpline, [&] {
-    return launch_spline_deposit(c->fixed, c->logn, d_pos, c->np, (float)h, mpm,
-                                 c->sorted ? &c->tmap : nullptr, d_delta, c->stream);
-  });
+  PM_TRY(run_spline_density(c, d_pos, h));
+  // delta = mass / mbar - 1 by the exact integer subtraction of the forward
+  // z pass (its spectrum is not used)
+  PM_TRY(timed(c, kcR2C, [&] {
+    return launch_r2c_z(c->logn, kSrcMass64, c->mass, c->delta, c->spec, c->tw, c->conv,
+                        c->stream);
+  }));
+  c->have_delta = true;
+  c->have_phi = false;
+  c->have_q = false;
+  c->fields_at_pos = false;
+  if (!c->has_q) PM_TRY(dev(launch_fill_zero(c->q, 4 * c->ncell, c->stream)));
+  return copy_out(c, d_delta, c->delta);
 }
 
 pm_status pm_spline_qforce(pm_ctx* c, const void* d_pos, const float* d_q, double h,
@@ -959,13 +1043,9 @@ pm_status pm_spline_step(pm_ctx* c, void* d_pos, float* d_vel, const double* tim
   // gradient of Q, [3][Np] floats each in the particle copy buffers
   float* gphi = reinterpret_cast<float*>(c->pos_tmp);
   float* gq = c->vel_tmp;
-  const float mpm = (float)((double)c->ncell / (double)c->np);
   auto forces = [&]() -> pm_status {
-    PM_TRY(timed(c, kcSpline, [&] {
-      return launch_spline_deposit(c->fixed, c->logn, d_pos, c->np, (float)h, mpm,
-                                   c->sorted ? &c->tmap : nullptr, c->delta, c->stream);
-    }));
-    PM_TRY(run_poisson(c, kSrcDelta, c->delta));
+    PM_TRY(run_spline_density(c, d_pos, h));
+    PM_TRY(run_poisson(c, kSrcMass64, c->mass));
     PM_TRY(timed(c, kcForce, [&] {
       return launch_force(c->fixed, false, c->logn, d_pos, c->phi, c->q, c->np, 1.0f, 0.0f,
                           gphi, c->stream);
@@ -975,7 +1055,7 @@ pm_status pm_spline_step(pm_ctx* c, void* d_pos, float* d_vel, const double* tim
       return timed(c, kcFill, [&] {
         return launch_fill_zero(gq, (12 * (size_t)c->np + 15) & ~(size_t)15, c->stream);
       });
-    PM_TRY(run_qpot(c, c->delta, false, kOutQ));
+    PM_TRY(run_qpot(c, c->delta, c->fixed, kOutQ));
     return timed(c, kcSplineForce, [&] {
       return launch_spline_qforce(c->fixed, c->logn, d_pos, c->np, c->q, (float)h, gq,
                                   c->stream);
@@ -1013,13 +1093,9 @@ pm_status pm_spline_energy(pm_ctx* c, const void* d_pos, const float* d_vel, dou
   if (!spline_h_ok(c, h)) return PM_EINVAL;
   if (!(a > 0.0) || !isfinite(a)) return PM_EINVAL;
   if (!c->p.comoving && a != 1.0) return PM_EINVAL;
-  const float mpm = (float)((double)c->ncell / (double)c->np);
-  PM_TRY(timed(c, kcSpline, [&] {
-    return launch_spline_deposit(c->fixed, c->logn, d_pos, c->np, (float)h, mpm,
-                                 c->sorted ? &c->tmap : nullptr, c->delta, c->stream);
-  }));
-  PM_TRY(run_poisson(c, kSrcDelta, c->delta));
-  PM_TRY(run_qpot(c, c->delta, false, kOutEnergy));
+  PM_TRY(run_spline_density(c, d_pos, h));
+  PM_TRY(run_poisson(c, kSrcMass64, c->mass));
+  PM_TRY(run_qpot(c, c->delta, c->fixed, kOutEnergy));
   PM_TRY(timed(c, kcReduce, [&] {
     return launch_reduce(c->partials, c->q_blocks, 2, c->result, c->stream);
   }));
@@ -1152,8 +1228,11 @@ pm_status pm_batch_step(pm_batch* b, void* d_pos, float* d_vel, int32_t nactive,
   if (!b || !d_pos || !d_vel || !slots || !times) return PM_EINVAL;
   if (nactive < 1 || nactive > b->slots) return PM_EINVAL;
   if (nsteps < 1 || nsteps > PM_BATCH_MAX_STEPS) return PM_EINVAL;
-  if (flags & ~(PM_CONTINUE | PM_SORT_EVERY(0xffff))) return PM_EINVAL;
+  if (flags & ~(PM_CONTINUE | PM_SORT_EVERY(0xffff) | PM_BATCH_GRAPH)) return PM_EINVAL;
   pm_ctx* c = &b->base;
+  const bool use_graph = (flags & PM_BATCH_GRAPH) != 0;
+  if (use_graph && c->stream == nullptr) return PM_EINVAL;   // no capture on the default stream
+  flags &= ~PM_BATCH_GRAPH;
   std::vector<char> seen(b->slots, 0);
   bool all_sorted = true, all_fields = true;
   for (int i = 0; i < nactive; ++i) {
@@ -1199,19 +1278,19 @@ pm_status pm_batch_step(pm_batch* b, void* d_pos, float* d_vel, int32_t nactive,
       }
     }
   }
-  {
-    // the buffer's previous copy was queued two calls ago; wait for it
-    const int hb = b->h_next;
-    b->h_next ^= 1;
-    PM_TRY(dev(hipEventSynchronize(b->h_done[hb])));
-    char* h = b->h_stage[hb];
-    const size_t coff = (size_t)(reinterpret_cast<char*>(b->d_consts) - b->ws);
-    memcpy(h, slots, 4 * (size_t)nactive);
-    memcpy(h + coff, tab.data(), sizeof(SlotConst) * tab.size());
+  // the buffer's previous copy was queued two calls ago; wait for it
+  const int hb = b->h_next;
+  b->h_next ^= 1;
+  PM_TRY(dev(hipEventSynchronize(b->h_done[hb])));
+  char* h = b->h_stage[hb];
+  const size_t coff = (size_t)(reinterpret_cast<char*>(b->d_consts) - b->ws);
+  memcpy(h, slots, 4 * (size_t)nactive);
+  memcpy(h + coff, tab.data(), sizeof(SlotConst) * tab.size());
+  auto upload = [&]() -> pm_status {
     PM_TRY(dev(hipMemcpyAsync(b->ws, h, coff + sizeof(SlotConst) * tab.size(),
                               hipMemcpyHostToDevice, c->stream)));
-    PM_TRY(dev(hipEventRecord(b->h_done[hb], c->stream)));
-  }
+    return dev(hipEventRecord(b->h_done[hb], c->stream));
+  };
   Batch bt;
   bt.slots = b->d_slots;
   bt.ws_stride = (long long)b->slot_stride;
@@ -1251,6 +1330,14 @@ pm_status pm_batch_step(pm_batch* b, void* d_pos, float* d_vel, int32_t nactive,
     sorted = true;
     return PM_OK;
   };
+  // Every kernel of the call, in stream order after the upload of its slot
+  // list and constant table.  Every launch argument depends only on the
+  // call's shape (the slot identities and the factors are read from the
+  // uploaded table), so a captured graph of one call's kernels serves every
+  // later call of the same shape.  The upload itself stays outside the graph:
+  // an event recorded in a capturing stream is not replayed, and the host
+  // must know when each staging buffer's copy is done.
+  auto enqueue = [&]() -> pm_status {
   if (!(flags & PM_CONTINUE)) {
     PM_TRY(dev(launch_fill_zero(c->mass, 8 * c->ncell + kStrayBytes, c->stream, bt)));
     if (c->fixed)
@@ -1291,8 +1378,37 @@ pm_status pm_batch_step(pm_batch* b, void* d_pos, float* d_vel, int32_t nactive,
     psi = k + 1 < nsteps;
     PM_TRY(fields(row(psi ? k + 1 : k), psi));
   }
-  PM_TRY(dev(launch_gather(c->fixed, true, false, c->logn, d_pos, d_vel, c->phi, c->q, c->np,
-                           unused, sorted ? &c->tmap : nullptr, nullptr, c->stream, row(nsteps))));
+  return dev(launch_gather(c->fixed, true, false, c->logn, d_pos, d_vel, c->phi, c->q, c->np,
+                           unused, sorted ? &c->tmap : nullptr, nullptr, c->stream, row(nsteps)));
+  };
+  PM_TRY(upload());
+  if (!use_graph) {
+    PM_TRY(enqueue());
+  } else {
+    const auto key = std::make_tuple((int)nactive, (int)nsteps, (int)flags, (int)all_sorted);
+    auto it = b->graphs.find(key);
+    if (it == b->graphs.end()) {
+      if (b->graphs.size() >= 64) {
+        for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.second);
+        b->graphs.clear();
+      }
+      PM_TRY(dev(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal)));
+      const pm_status st = enqueue();
+      hipGraph_t graph = nullptr;
+      const hipError_t e = hipStreamEndCapture(c->stream, &graph);
+      if (st != PM_OK || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st != PM_OK ? st : PM_EDEVICE;
+      }
+      hipGraphExec_t exec = nullptr;
+      const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ei != hipSuccess) return PM_EDEVICE;
+      it = b->graphs.emplace(key, exec).first;
+    }
+    PM_TRY(dev(hipGraphLaunch(it->second, c->stream)));
+  }
+  sorted = all_sorted || (sort_every > 0) || sorted;
   for (int i = 0; i < nactive; ++i) {
     b->fields_ok[slots[i]] = 1;
     if (sorted) b->sorted[slots[i]] = 1;

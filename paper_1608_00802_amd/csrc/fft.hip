@@ -129,6 +129,11 @@ __device__ __forceinline__ void fft_rows(float2* __restrict__ buf, const float2*
 #ifndef FDM_FFTZ_XG
 #define FDM_FFTZ_XG 4   // 512^3 (8 rows per block): C2R 374 -> 351 us
 #endif
+#ifndef FDM_FFT_Z_ELEMS_512
+// z-pass elements per block at N = 512: 16 rows, whole 128-byte lines of the
+// kz-major spectrum per row (C2R 352 -> 279 us, R2C 482 -> 436 us)
+#define FDM_FFT_Z_ELEMS_512 8192
+#endif
 #ifndef FDM_FFT_Z_ELEMS
 #define FDM_FFT_Z_ELEMS 4096
 #endif
@@ -137,7 +142,8 @@ __device__ __forceinline__ void fft_rows(float2* __restrict__ buf, const float2*
 // another's loads (256^3: 30 us less per step than tiles twice as large).
 template <int N>
 struct Tiles {
-  static constexpr int ZE = FDM_FFT_Z_ELEMS;
+  static constexpr int ZE = (N >= 512 && FDM_FFT_Z_ELEMS_512) ? FDM_FFT_Z_ELEMS_512
+                                                               : FDM_FFT_Z_ELEMS;
   static constexpr int TZ = (ZE / N < N) ? ZE / N : N;   // rows per z-pass block
   // below 16 rows a block's kz-major accesses cover part of each 128-byte
   // line: the blocks sharing a line go to one XCD together
@@ -152,6 +158,18 @@ struct Tiles {
 // factors) instead of one per radix-4 stage.  The y and x passes use this
 // form; the z passes (with their real-data packing) use fft_rows.
 constexpr int kRegBlock = 128;   // threads per block of the register-FFT y passes
+#ifndef FDM_FFTX_XT
+#define FDM_FFTX_XT 0      // x-pass threads per block (0: 64 up to N = 256, 128 above)
+#endif
+#ifndef FDM_FFTX_TC
+#define FDM_FFTX_TC 0      // x-pass columns per block (0: 4 up to N = 256, 8 above)
+#endif
+#ifndef FDM_FFTX_ORDER
+#define FDM_FFTX_ORDER 0   // lanes across the block's columns (see x_item)
+#endif
+#ifndef FDM_FFTX_PAD
+#define FDM_FFTX_PAD -1    // extra float2 between the x pass's LDS columns (-1: per N)
+#endif
 
 template <int L>
 struct Split {
@@ -310,15 +328,34 @@ struct RegTiles {
   static constexpr int RMAX = R1 > R2 ? R1 : R2;
   static constexpr int RY0 = kRegBlock / R2;                       // y-pass rows per block
   static constexpr int RY = RY0 < N ? RY0 : N;
-  // x pass: 64 threads and 4 columns up to N = 256 (36 against 46 us per
-  // pass at 256^3 with 128 threads and 8 columns), 128 and 8 above (380
-  // against 466 us at 512^3); the blocks that share a 128-byte line of a
-  // column run are grouped on one XCD
-  static constexpr int XT = N <= 256 ? 64 : 128;                   // x-pass threads per block
-  static constexpr int TC0 = N <= 256 ? ((XT / RMAX > 4) ? XT / RMAX : 4) : 8;
+  // x pass: 256 threads and 16 columns from N = 256 on (whole 128-byte lines
+  // per row; 256^3: 29.6 us against 37.5 with 64 threads and 4 columns and
+  // 31.8 with 128 and 8; 512^3: 266 against 385 us with 128 and 8), 64 and 4
+  // below; blocks that share a line of a column run are grouped on one XCD
+  static constexpr int XT = FDM_FFTX_XT ? FDM_FFTX_XT : (N < 256 ? 64 : 256);  // threads
+  static constexpr int TC0 =
+      FDM_FFTX_TC ? FDM_FFTX_TC : (N < 256 ? ((XT / RMAX > 4) ? XT / RMAX : 4) : 16);
   static constexpr int TC = TC0 < N ? TC0 : N;                     // x-pass columns per block
   static constexpr int XG = TC < 16 ? 16 / TC : 1;                 // XCD group
+  // padding between the columns of the LDS exchange (2 entries with 16
+  // columns: their 128-byte runs otherwise start in the same banks)
+  static constexpr int PAD = FDM_FFTX_PAD >= 0 ? FDM_FFTX_PAD : (N >= 256 ? 2 : 0);
 };
+
+// Work item `it` of the x pass: column c of the block's TC columns and index
+// i < M along the transform.  Columns fastest across lanes: every group of
+// four lanes loads one 32-byte run of a row (index fastest, with the same
+// cache lines touched, took 46 instead of 38 us per pass at 256^3).
+template <int TC, int M>
+__device__ __forceinline__ void x_item(int it, int& c, int& i) {
+  if constexpr (FDM_FFTX_ORDER != 0) {
+    c = it / M;
+    i = it % M;
+  } else {
+    c = it % TC;
+    i = it / TC;
+  }
+}
 
 template <int LOGN, bool INV>
 __global__ void __launch_bounds__(kRegBlock) k_fft_y_reg(float2* __restrict__ spec,
@@ -386,7 +423,7 @@ __global__ void __launch_bounds__(RegTiles<1 << LOGN>::XT) k_fft_x_green_reg(flo
   // forward exchange ex[c][n2][k1] (k1 < R1, padded), inverse ex[c][k1][k1']
   // (k1' < R2, padded); one buffer, the larger of the two
   constexpr int XF = R2 * (R1 + 1), XI = R1 * (R2 + 1);
-  constexpr int XS = XF > XI ? XF : XI;
+  constexpr int XS = (XF > XI ? XF : XI) + RegTiles<N>::PAD;
   constexpr int NA = TC * R2, NB = TC * R1;   // items: first factor (R1 values) / second (R2 values)
   constexpr int PA = (NA + XT - 1) / XT, PB = (NB + XT - 1) / XT;
   __shared__ float2 ex[TC * XS];
@@ -403,7 +440,8 @@ __global__ void __launch_bounds__(RegTiles<1 << LOGN>::XT) k_fft_x_green_reg(flo
   for (int p = 0; p < PA; ++p) {
     const int it = tid + p * XT;
     if (NA % XT == 0 || it < NA) {
-      const int c = it % TC, n2 = it / TC;
+      int c, n2;
+      x_item<TC, R2>(it, c, n2);
 #pragma unroll
       for (int n1 = 0; n1 < R1; ++n1) v[p][n1] = at(R2 * n1 + n2, c);
     }
@@ -417,7 +455,8 @@ __global__ void __launch_bounds__(RegTiles<1 << LOGN>::XT) k_fft_x_green_reg(flo
   for (int p = 0; p < PA; ++p) {
     const int it = tid + p * XT;
     if (NA % XT == 0 || it < NA) {
-      const int c = it % TC, n2 = it / TC;
+      int c, n2;
+      x_item<TC, R2>(it, c, n2);
       fft_first<N, R1, false>(v[p], n2, tws);
 #pragma unroll
       for (int k1 = 0; k1 < R1; ++k1) ex[c * XS + n2 * (R1 + 1) + k1] = v[p][k1];
@@ -432,7 +471,8 @@ __global__ void __launch_bounds__(RegTiles<1 << LOGN>::XT) k_fft_x_green_reg(flo
   for (int p = 0; p < PB; ++p) {
     const int it = tid + p * XT;
     if (NB % XT == 0 || it < NB) {
-      const int c = it % TC, k1 = it / TC;
+      int c, k1;
+      x_item<TC, R1>(it, c, k1);
 #pragma unroll
       for (int n2 = 0; n2 < R2; ++n2) u[p][n2] = ex[c * XS + n2 * (R1 + 1) + k1];
       dft_reg<R2, false, N / R2>(u[p], tws);
@@ -451,7 +491,8 @@ __global__ void __launch_bounds__(RegTiles<1 << LOGN>::XT) k_fft_x_green_reg(flo
   for (int p = 0; p < PB; ++p) {
     const int it = tid + p * XT;
     if (NB % XT == 0 || it < NB) {
-      const int c = it % TC, k1 = it / TC;
+      int c, k1;
+      x_item<TC, R1>(it, c, k1);
 #pragma unroll
       for (int j = 0; j < R2; ++j) ex[c * XS + k1 * (R2 + 1) + j] = u[p][j];
     }
@@ -462,7 +503,8 @@ __global__ void __launch_bounds__(RegTiles<1 << LOGN>::XT) k_fft_x_green_reg(flo
   for (int p = 0; p < PA; ++p) {
     const int it = tid + p * XT;
     if (NA % XT == 0 || it < NA) {
-      const int c = it % TC, j = it / TC;
+      int c, j;
+      x_item<TC, R2>(it, c, j);
 #pragma unroll
       for (int k1 = 0; k1 < R1; ++k1) v[p][k1] = ex[c * XS + k1 * (R2 + 1) + j];
       dft_reg<R1, true, N / R1>(v[p], tws);
@@ -600,7 +642,8 @@ __global__ void __launch_bounds__(RegTiles<1 << LOGN>::XT) k_fft_x_power_reg(
   for (int p = 0; p < PA; ++p) {
     const int it = tid + p * XT;
     if (NA % XT == 0 || it < NA) {
-      const int c = it % TC, n2 = it / TC;
+      int c, n2;
+      x_item<TC, R2>(it, c, n2);
 #pragma unroll
       for (int n1 = 0; n1 < R1; ++n1) v[p][n1] = at(R2 * n1 + n2, c);
     }
@@ -612,7 +655,8 @@ __global__ void __launch_bounds__(RegTiles<1 << LOGN>::XT) k_fft_x_power_reg(
   for (int p = 0; p < PA; ++p) {
     const int it = tid + p * XT;
     if (NA % XT == 0 || it < NA) {
-      const int c = it % TC, n2 = it / TC;
+      int c, n2;
+      x_item<TC, R2>(it, c, n2);
       fft_first<N, R1, false>(v[p], n2, tws);
 #pragma unroll
       for (int k1 = 0; k1 < R1; ++k1) ex[c * XF + n2 * (R1 + 1) + k1] = v[p][k1];
@@ -624,7 +668,8 @@ __global__ void __launch_bounds__(RegTiles<1 << LOGN>::XT) k_fft_x_power_reg(
   for (int p = 0; p < PB; ++p) {
     const int it = tid + p * XT;
     if (NB % XT == 0 || it < NB) {
-      const int c = it % TC, k1 = it / TC;
+      int c, k1;
+      x_item<TC, R1>(it, c, k1);
       float2 u[R2];
 #pragma unroll
       for (int n2 = 0; n2 < R2; ++n2) u[n2] = ex[c * XF + n2 * (R1 + 1) + k1];

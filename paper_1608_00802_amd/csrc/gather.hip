@@ -163,7 +163,35 @@ __device__ __forceinline__ void new_weights(const uint32_t unew[3], const float 
     float_weights<LOGN>(xnew[0], xnew[1], xnew[2], ix, iy, iz, w);
 }
 
-template <int LOGN, bool FIXED, bool HAS_Q, int MODE, bool DEP>
+// FP64 sum of one value per thread over the block (all threads call it);
+// the wave sums go through `red` (one slot per wave).
+template <int BLOCK>
+__device__ __forceinline__ double block_total(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < BLOCK / 64; ++w) t += red[w];
+  return t;
+}
+
+// Energy form of the kick: -grad phi and -grad Q interpolated separately
+// (gp, gq); the closing half-kick of the previous step gives the momentum at
+// the synchronised time (vk, whose |vk|^2 enters K), the opening half-kick of
+// this step the kick applied on top of it (g).
+__device__ __forceinline__ void split_kick(const GatherConst& gc, const float vin[3],
+                                           const float gp[3], const float gq[3], float vk[3],
+                                           float g[3], double& ksum) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    vk[d] = vin[d] + fmaf(gc.fq, gq[d], gc.fg * gp[d]);
+    g[d] = fmaf(gc.oq, gq[d], gc.og * gp[d]);
+    ksum += (double)vk[d] * (double)vk[d];
+  }
+}
+
+template <int LOGN, bool FIXED, bool HAS_Q, int MODE, bool DEP, bool EN = false>
 __global__ void __launch_bounds__(kBlock) k_gather(void* __restrict__ pos,
                                                    float* __restrict__ vel,
                                                    const float* __restrict__ phi,
@@ -191,27 +219,45 @@ __global__ void __launch_bounds__(kBlock) k_gather(void* __restrict__ pos,
   constexpr int N = 1 << LOGN;
   constexpr int MASK = N - 1;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  double ksum = 0.0;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += stride) {
     int ic[3];
     float f[3], xf[3], vin[3];
     uint32_t u[3], raw[3];
     load_particle(pos, MODE == kForce ? nullptr : vel, np, p, raw, vin);
     decode_cell<LOGN, FIXED>(raw, ic, f, u, xf);
-    float g[3];
-    interp_grad(f, [&](int a, int b, int c) {
-      const size_t idx = ((size_t)((ic[0] + a - 1) & MASK) * N + ((ic[1] + b - 1) & MASK)) * N +
-                         ((ic[2] + c - 1) & MASK);
-      return mesh_f<LOGN, HAS_Q>(phi, q, gc, idx);
-    }, g);
+    auto node = [&](int a, int b, int c) {
+      return ((size_t)((ic[0] + a - 1) & MASK) * N + ((ic[1] + b - 1) & MASK)) * N +
+             ((ic[2] + c - 1) & MASK);
+    };
+    float g[3], vk[3];
+    if constexpr (EN) {
+      float gp[3], gq[3] = {0.0f, 0.0f, 0.0f};
+      interp_grad(f, [&](int a, int b, int c) { return phi[node(a, b, c)]; }, gp);
+      if constexpr (HAS_Q)
+        interp_grad(f, [&](int a, int b, int c) { return q[node(a, b, c)]; }, gq);
+      split_kick(gc, vin, gp, gq, vk, g, ksum);
+    } else {
+      interp_grad(f, [&](int a, int b, int c) {
+        return mesh_f<LOGN, HAS_Q>(phi, q, gc, node(a, b, c));
+      }, g);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) vk[d] = vin[d];
+    }
     uint32_t unew[3];
     float xnew[3];
-    push<LOGN, FIXED, MODE>(pos, vel, acc, np, p, g, vin, u, xf, gc.fd_units, unew, xnew, mass_v);
+    push<LOGN, FIXED, MODE>(pos, vel, acc, np, p, g, vk, u, xf, gc.fd_units, unew, xnew, mass_v);
     if constexpr (DEP) {
       int jx, jy, jz;
       T w[8];
       new_weights<LOGN, FIXED>(unew, xnew, jx, jy, jz, w);
       deposit_global<LOGN>(static_cast<T*>(mass_v), jx, jy, jz, w);
     }
+  }
+  if constexpr (EN) {
+    __shared__ double kred[kBlock / 64];
+    const double t = block_total<kBlock>(ksum, kred);
+    if (threadIdx.x == 0) gc.kpart[blockIdx.x] = t;
   }
 }
 
@@ -221,7 +267,7 @@ __global__ void __launch_bounds__(kBlock) k_gather(void* __restrict__ pos,
 // particles that left it read the mesh directly.
 // WIDE: a one-cell larger gather window and a two-cell deposit halo, for
 // steps whose particles have moved since the sort in a clustered state.
-template <int LOGN, bool FIXED, bool HAS_Q, int MODE, bool DEP, int WIDE = 0>
+template <int LOGN, bool FIXED, bool HAS_Q, int MODE, bool DEP, int WIDE = 0, bool EN = false>
 __global__ void __launch_bounds__(kGatherBlock) k_gather_tiled(void* __restrict__ pos,
                                                          float* __restrict__ vel,
                                                          const float* __restrict__ phi,
@@ -258,11 +304,17 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather_tiled(void* __restrict_
   constexpr int NTY = N / TY, NTZ = N / TZ;
   constexpr int DX = TX + 1 + 2 * HD, DY = TY + 1 + 2 * HD, DZ = TZ + 1 + 2 * HD;
   __shared__ float win[WX * WY * WZ];
+  // energy form: win holds phi and winq holds Q (interpolated separately)
+  __shared__ float winq[EN && HAS_Q ? WX * WY * WZ : 1];
   __shared__ T dacc[DEP ? DX * DY * DZ : 1];
   __shared__ unsigned n_stray;
   int t;
   unsigned lo, hi;
-  if (!chunk_of(tm, t, lo, hi)) return;
+  if (!chunk_of(tm, t, lo, hi)) {
+    if constexpr (EN)
+      if (threadIdx.x == 0) gc.kpart[blockIdx.x] = 0.0;
+    return;
+  }
   if (threadIdx.x == 0) n_stray = 0;
   // the first particles' loads are in flight while the window is staged;
   // afterwards particle p + PF * kGatherBlock is loaded while p is processed
@@ -275,7 +327,15 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather_tiled(void* __restrict_
     if (pk < hi) load_particle(pos, vel, np, pk, raw_n[k], vin_n[k]);
   }
   const int ox = (t / (NTY * NTZ)) * TX, oy = ((t / NTZ) % NTY) * TY, oz = (t % NTZ) * TZ;
-  if constexpr (HAS_Q) {
+  if constexpr (EN) {
+    for (int c = threadIdx.x; c < WX * WY * WZ; c += kGatherBlock) {
+      const int lx = c / (WY * WZ), ly = (c / WZ) % WY, lz = c % WZ;
+      const size_t idx = ((size_t)((ox - 1 - HG + lx) & MASK) * N +
+                          ((oy - 1 - HG + ly) & MASK)) * N + ((oz - 1 - HG + lz) & MASK);
+      win[c] = phi[idx];
+      if constexpr (HAS_Q) winq[c] = q[idx];
+    }
+  } else if constexpr (HAS_Q) {
     for (int c = threadIdx.x; c < WX * WY * WZ; c += kGatherBlock) {
       const int lx = c / (WY * WZ), ly = (c / WZ) % WY, lz = c % WZ;
       const size_t idx = ((size_t)((ox - 1 - HG + lx) & MASK) * N +
@@ -307,6 +367,7 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather_tiled(void* __restrict_
   if constexpr (DEP)
     for (int c = threadIdx.x; c < DX * DY * DZ; c += kGatherBlock) dacc[c] = (T)0;
   __syncthreads();
+  double ksum = 0.0;
   for (unsigned p = lo + threadIdx.x; p < hi; p += kGatherBlock) {
     int ic[3];
     float f[3], xf[3], vin[3];
@@ -328,21 +389,39 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather_tiled(void* __restrict_
     decode_cell<LOGN, FIXED>(raw, ic, f, u, xf);
     const int rx = (ic[0] - ox + HG) & MASK, ry = (ic[1] - oy + HG) & MASK,
               rz = (ic[2] - oz + HG) & MASK;
-    float g[3];
-    if (rx < TX + 2 * HG && ry < TY + 2 * HG && rz < TZ + 2 * HG) {
-      interp_grad(f, [&](int a, int b, int c) {
-        return win[((rx + a) * WY + ry + b) * WZ + rz + c];
-      }, g);
+    const bool in_win = rx < TX + 2 * HG && ry < TY + 2 * HG && rz < TZ + 2 * HG;
+    auto lds = [&](int a, int b, int c) { return ((rx + a) * WY + ry + b) * WZ + rz + c; };
+    auto node = [&](int a, int b, int c) {
+      return ((size_t)((ic[0] + a - 1) & MASK) * N + ((ic[1] + b - 1) & MASK)) * N +
+             ((ic[2] + c - 1) & MASK);
+    };
+    float g[3], vk[3];
+    if constexpr (EN) {
+      float gp[3], gq[3] = {0.0f, 0.0f, 0.0f};
+      if (in_win) {
+        interp_grad(f, [&](int a, int b, int c) { return win[lds(a, b, c)]; }, gp);
+        if constexpr (HAS_Q)
+          interp_grad(f, [&](int a, int b, int c) { return winq[lds(a, b, c)]; }, gq);
+      } else {
+        interp_grad(f, [&](int a, int b, int c) { return phi[node(a, b, c)]; }, gp);
+        if constexpr (HAS_Q)
+          interp_grad(f, [&](int a, int b, int c) { return q[node(a, b, c)]; }, gq);
+      }
+      split_kick(gc, vin, gp, gq, vk, g, ksum);
     } else {
-      interp_grad(f, [&](int a, int b, int c) {
-        const size_t idx = ((size_t)((ic[0] + a - 1) & MASK) * N + ((ic[1] + b - 1) & MASK)) * N +
-                           ((ic[2] + c - 1) & MASK);
-        return mesh_f<LOGN, HAS_Q>(phi, q, gc, idx);
-      }, g);
+      if (in_win) {
+        interp_grad(f, [&](int a, int b, int c) { return win[lds(a, b, c)]; }, g);
+      } else {
+        interp_grad(f, [&](int a, int b, int c) {
+          return mesh_f<LOGN, HAS_Q>(phi, q, gc, node(a, b, c));
+        }, g);
+      }
+#pragma unroll
+      for (int d = 0; d < 3; ++d) vk[d] = vin[d];
     }
     uint32_t unew[3];
     float xnew[3];
-    push<LOGN, FIXED, MODE>(pos, vel, acc, np, p, g, vin, u, xf, gc.fd_units, unew, xnew, mass_v);
+    push<LOGN, FIXED, MODE>(pos, vel, acc, np, p, g, vk, u, xf, gc.fd_units, unew, xnew, mass_v);
     if constexpr (DEP) {
       int jx, jy, jz;
       T w[8];
@@ -368,6 +447,11 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather_tiled(void* __restrict_
       if (m && (threadIdx.x & 63) == __ffsll((long long)__ballot(1)) - 1)
         atomicAdd(&n_stray, (unsigned)__popcll(m));
     }
+  }
+  if constexpr (EN) {
+    __shared__ double kred[kGatherBlock / 64];
+    const double kt = block_total<kGatherBlock>(ksum, kred);
+    if (threadIdx.x == 0) gc.kpart[blockIdx.x] = kt;
   }
   if constexpr (DEP) {
     __syncthreads();
@@ -406,55 +490,59 @@ static unsigned grid_particles(int64_t np) {
   return (unsigned)b;
 }
 
-template <int LN, int MODE, bool DEP>
+template <int LN, int MODE, bool DEP, bool EN = false>
 static void launch_mode_tiled(bool fixed, bool has_q, hipStream_t s, void* pos, float* vel,
                               const float* phi, const float* q, int64_t np, const TileMap& tm,
                               const GatherConst& gc, float* acc, void* mass, const Batch& bt) {
   const dim3 g(tiled_grid(np, tm.tiles), bt.count);
   if (fixed && has_q)
-    hipLaunchKernelGGL((k_gather_tiled<LN, true, true, MODE, DEP>), g, dim3(kGatherBlock), 0, s, pos,
-                       vel, phi, q, np, tm, gc, acc, mass, bt);
+    hipLaunchKernelGGL((k_gather_tiled<LN, true, true, MODE, DEP, 0, EN>), g, dim3(kGatherBlock),
+                       0, s, pos, vel, phi, q, np, tm, gc, acc, mass, bt);
   else if (fixed)
-    hipLaunchKernelGGL((k_gather_tiled<LN, true, false, MODE, DEP>), g, dim3(kGatherBlock), 0, s, pos,
-                       vel, phi, q, np, tm, gc, acc, mass, bt);
+    hipLaunchKernelGGL((k_gather_tiled<LN, true, false, MODE, DEP, 0, EN>), g, dim3(kGatherBlock),
+                       0, s, pos, vel, phi, q, np, tm, gc, acc, mass, bt);
   else if (has_q)
-    hipLaunchKernelGGL((k_gather_tiled<LN, false, true, MODE, DEP>), g, dim3(kGatherBlock), 0, s, pos,
-                       vel, phi, q, np, tm, gc, acc, mass, bt);
+    hipLaunchKernelGGL((k_gather_tiled<LN, false, true, MODE, DEP, 0, EN>), g, dim3(kGatherBlock),
+                       0, s, pos, vel, phi, q, np, tm, gc, acc, mass, bt);
   else
-    hipLaunchKernelGGL((k_gather_tiled<LN, false, false, MODE, DEP>), g, dim3(kGatherBlock), 0, s, pos,
-                       vel, phi, q, np, tm, gc, acc, mass, bt);
+    hipLaunchKernelGGL((k_gather_tiled<LN, false, false, MODE, DEP, 0, EN>), g,
+                       dim3(kGatherBlock), 0, s, pos, vel, phi, q, np, tm, gc, acc, mass, bt);
 }
 
-template <int LN, int MODE, bool DEP>
+template <int LN, int MODE, bool DEP, bool EN = false>
 static void launch_mode(bool fixed, bool has_q, dim3 g, hipStream_t s, void* pos, float* vel,
                         const float* phi, const float* q, int64_t np, const GatherConst& gc,
                         float* acc, void* mass, const Batch& bt) {
   g.y = bt.count;
   if (fixed && has_q)
-    hipLaunchKernelGGL((k_gather<LN, true, true, MODE, DEP>), g, dim3(kBlock), 0, s, pos, vel, phi,
-                       q, np, gc, acc, mass, bt);
+    hipLaunchKernelGGL((k_gather<LN, true, true, MODE, DEP, EN>), g, dim3(kBlock), 0, s, pos, vel,
+                       phi, q, np, gc, acc, mass, bt);
   else if (fixed)
-    hipLaunchKernelGGL((k_gather<LN, true, false, MODE, DEP>), g, dim3(kBlock), 0, s, pos, vel,
-                       phi, q, np, gc, acc, mass, bt);
+    hipLaunchKernelGGL((k_gather<LN, true, false, MODE, DEP, EN>), g, dim3(kBlock), 0, s, pos,
+                       vel, phi, q, np, gc, acc, mass, bt);
   else if (has_q)
-    hipLaunchKernelGGL((k_gather<LN, false, true, MODE, DEP>), g, dim3(kBlock), 0, s, pos, vel,
-                       phi, q, np, gc, acc, mass, bt);
+    hipLaunchKernelGGL((k_gather<LN, false, true, MODE, DEP, EN>), g, dim3(kBlock), 0, s, pos,
+                       vel, phi, q, np, gc, acc, mass, bt);
   else
-    hipLaunchKernelGGL((k_gather<LN, false, false, MODE, DEP>), g, dim3(kBlock), 0, s, pos, vel,
-                       phi, q, np, gc, acc, mass, bt);
+    hipLaunchKernelGGL((k_gather<LN, false, false, MODE, DEP, EN>), g, dim3(kBlock), 0, s, pos,
+                       vel, phi, q, np, gc, acc, mass, bt);
 }
 
-template <int LN>
+template <int LN, bool EN = false>
 static void launch_wide(bool has_q, hipStream_t s, void* pos, float* vel, const float* phi,
                         const float* q, int64_t np, const TileMap& tm, const GatherConst& gc,
                         void* mass, const Batch& bt) {
   const dim3 g(tiled_grid(np, tm.tiles), bt.count);
   if (has_q)
-    hipLaunchKernelGGL((k_gather_tiled<LN, true, true, kKickDrift, true, 1>), g,
+    hipLaunchKernelGGL((k_gather_tiled<LN, true, true, kKickDrift, true, 1, EN>), g,
                        dim3(kGatherBlock), 0, s, pos, vel, phi, q, np, tm, gc, nullptr, mass, bt);
   else
-    hipLaunchKernelGGL((k_gather_tiled<LN, true, false, kKickDrift, true, 1>), g,
+    hipLaunchKernelGGL((k_gather_tiled<LN, true, false, kKickDrift, true, 1, EN>), g,
                        dim3(kGatherBlock), 0, s, pos, vel, phi, q, np, tm, gc, nullptr, mass, bt);
+}
+
+unsigned gather_blocks(int64_t np, const TileMap* tm) {
+  return tm ? tiled_grid(np, tm->tiles) : grid_particles(np);
 }
 
 hipError_t launch_gather(bool fixed, bool has_q, bool drift, int logn, void* pos, float* vel,
@@ -464,33 +552,44 @@ hipError_t launch_gather(bool fixed, bool has_q, bool drift, int logn, void* pos
   const dim3 g(grid_particles(np));
   const bool dep = drift && deposit_mass != nullptr;
   const bool copy = !drift && tm && pos_out && vel_out;
-#define L_(LN)                                                                                 \
-  {                                                                                            \
-    if (copy)                                                                                  \
-      launch_mode_tiled<LN, kKickCopy, false>(fixed, has_q, s, pos, vel, phi, q, np, *tm, gc,  \
-                                              vel_out, pos_out, bt);                           \
-    else if (tm && dep && wide && fixed)                                                       \
-      launch_wide<LN>(has_q, s, pos, vel, phi, q, np, *tm, gc, deposit_mass, bt);              \
-    else if (tm && dep)                                                                        \
-      launch_mode_tiled<LN, kKickDrift, true>(fixed, has_q, s, pos, vel, phi, q, np, *tm, gc,  \
-                                              nullptr, deposit_mass, bt);                      \
-    else if (tm && drift)                                                                      \
-      launch_mode_tiled<LN, kKickDrift, false>(fixed, has_q, s, pos, vel, phi, q, np, *tm, gc, \
-                                               nullptr, nullptr, bt);                          \
-    else if (tm)                                                                               \
-      launch_mode_tiled<LN, kKick, false>(fixed, has_q, s, pos, vel, phi, q, np, *tm, gc,      \
-                                          nullptr, nullptr, bt);                               \
-    else if (dep)                                                                              \
-      launch_mode<LN, kKickDrift, true>(fixed, has_q, g, s, pos, vel, phi, q, np, gc, nullptr, \
-                                        deposit_mass, bt);                                     \
-    else if (drift)                                                                            \
-      launch_mode<LN, kKickDrift, false>(fixed, has_q, g, s, pos, vel, phi, q, np, gc,         \
-                                         nullptr, nullptr, bt);                                \
-    else                                                                                       \
-      launch_mode<LN, kKick, false>(fixed, has_q, g, s, pos, vel, phi, q, np, gc, nullptr,     \
-                                    nullptr, bt);                                              \
+  // the energy form exists for the launches a step makes: the fused
+  // gather-deposit and the closing half-kick (with or without the copy back)
+  if (gc.kpart && ((drift && !dep) || bt.slots)) return hipErrorInvalidValue;
+#define L_(LN, EN)                                                                               \
+  {                                                                                              \
+    if (copy)                                                                                    \
+      launch_mode_tiled<LN, kKickCopy, false, EN>(fixed, has_q, s, pos, vel, phi, q, np, *tm,    \
+                                                  gc, vel_out, pos_out, bt);                     \
+    else if (tm && dep && wide && fixed)                                                         \
+      launch_wide<LN, EN>(has_q, s, pos, vel, phi, q, np, *tm, gc, deposit_mass, bt);            \
+    else if (tm && dep)                                                                          \
+      launch_mode_tiled<LN, kKickDrift, true, EN>(fixed, has_q, s, pos, vel, phi, q, np, *tm,    \
+                                                  gc, nullptr, deposit_mass, bt);                \
+    else if (tm && drift)                                                                        \
+      launch_mode_tiled<LN, kKickDrift, false>(fixed, has_q, s, pos, vel, phi, q, np, *tm, gc,   \
+                                               nullptr, nullptr, bt);                            \
+    else if (tm)                                                                                 \
+      launch_mode_tiled<LN, kKick, false, EN>(fixed, has_q, s, pos, vel, phi, q, np, *tm, gc,    \
+                                              nullptr, nullptr, bt);                             \
+    else if (dep)                                                                                \
+      launch_mode<LN, kKickDrift, true, EN>(fixed, has_q, g, s, pos, vel, phi, q, np, gc,        \
+                                            nullptr, deposit_mass, bt);                          \
+    else if (drift)                                                                              \
+      launch_mode<LN, kKickDrift, false>(fixed, has_q, g, s, pos, vel, phi, q, np, gc, nullptr,  \
+                                         nullptr, bt);                                           \
+    else                                                                                         \
+      launch_mode<LN, kKick, false, EN>(fixed, has_q, g, s, pos, vel, phi, q, np, gc, nullptr,   \
+                                        nullptr, bt);                                            \
   }
-  FDM_LOGN_SWITCH(logn, L_)
+#define E_(LN)          \
+  {                     \
+    if (gc.kpart)       \
+      L_(LN, true)      \
+    else                \
+      L_(LN, false)     \
+  }
+  FDM_LOGN_SWITCH(logn, E_)
+#undef E_
 #undef L_
   return hipGetLastError();
 }

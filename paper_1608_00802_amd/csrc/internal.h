@@ -182,6 +182,19 @@ struct GatherConst {
   double fd_units;    // drift factor times 2^(32 - log2 N) (fixed) or drift factor (float)
   int psi = 0;        // phi holds psi with its factors applied: fg = 1, fq unused, and a
                       // batch's per-slot kick factors are not applied again
+  // Energy form (kpart set): phi and Q are interpolated separately; (fg, fq)
+  // is the closing half-kick of the previous step, which gives the momentum
+  // at the synchronised time, and (og, oq) the opening half-kick of this one.
+  // Each block stores its FP64 sum of |p|^2 at the synchronised time in
+  // kpart[blockIdx.x] (zero for blocks without particles).
+  float og = 0.0f, oq = 0.0f;
+  double* kpart = nullptr;
+};
+
+// Scale factors that turn the per-block partial sums of one synchronised
+// state into K, W, U (pm_energies units).
+struct EnergyScale {
+  double k, w, u;
 };
 
 // ---- deposit.hip
@@ -278,6 +291,11 @@ hipError_t launch_qpot(int logn, bool fixed, int out, const float* delta,
 int qpot_blocks(int logn);
 hipError_t launch_reduce(const double* partials, int nblocks, int ncomp, double* out,
                          hipStream_t s, const Batch& bt = Batch());
+// out[0..3] = K, W, U, K + W + U from the stencil's (delta phi, gradient)
+// partials of nq blocks and the gather's |p|^2 partials of nk blocks, each
+// summed in a fixed order and scaled by sc.
+hipError_t launch_energy_row(const double* qpart, int nq, const double* kpart, int nk,
+                             EnergyScale sc, double* out, hipStream_t s);
 
 // ---- gather.hip
 // wide (fixed point, fused deposit on a sorted context): the larger windows
@@ -296,6 +314,8 @@ hipError_t launch_force(bool fixed, bool has_q, int logn, const void* pos,
 hipError_t launch_kinetic(const float* vel, int64_t np, double* partials, int nblocks,
                           hipStream_t s, const Batch& bt = Batch());
 int kinetic_blocks(int64_t np);
+// Blocks of a gather launch (the number of |p|^2 partials of its energy form).
+unsigned gather_blocks(int64_t np, const TileMap* tm);
 
 // ---- fft.hip, power spectrum: the forward x transform of a spectrum after
 // r2c_z and the forward y pass, |X|^2 binned into shells b = 1..nb of integer
@@ -306,12 +326,12 @@ hipError_t launch_fft_x_power(int logn, const float2* spec, const float2* tw, in
                               double* partials, double* out, hipStream_t s);
 
 // ---- spline.hip: the spline kernel of Eq. (15) with smoothing length h
-// (cells); delta (N^3) is filled with -1 and receives the deposit of
-// mass_per_mean = N^3 / Np per particle; acc is [3][np].
+// (cells); mass (N^3, zeroed by the caller) receives sum_i W(|x_j - q_i|)
+// in units of 2^-40 particle masses per cell volume (the units of the CIC
+// mass mesh); acc is [3][np].
 // With tm (sorted context) the deposit sums each tile chunk in LDS first.
 hipError_t launch_spline_deposit(bool fixed, int logn, const void* pos, int64_t np, float h,
-                                 float mass_per_mean, const TileMap* tm, float* delta,
-                                 hipStream_t s);
+                                 const TileMap* tm, unsigned long long* mass, hipStream_t s);
 hipError_t launch_spline_qforce(bool fixed, int logn, const void* pos, int64_t np,
                                 const float* q, float h, float* acc, hipStream_t s);
 // The spline step's half-kick (v += fg g_phi + fq g_q) and drift (x += fd v).

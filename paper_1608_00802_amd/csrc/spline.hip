@@ -5,6 +5,16 @@
 // sign makes a = -grad Q, the particle derivative of the discrete K_rho).
 // Every node within h of a particle is visited: for h = 3.5 cells a cube of
 // 8^3 candidate nodes, about 180 of them inside the support.
+//
+// The density is summed in integers: each kernel value W (per unit particle
+// mass, cells^-3, at most 8 / (pi h^3)) is rounded once to a multiple of 2^-40
+// and added as an unsigned 64-bit integer, in the units of the
+// cloud-in-cell deposit (one particle = 2^40), into the context's mass mesh.
+// Integer sums commute, so the mesh is bitwise independent of particle order
+// and scheduling (tiled or direct, run to run), the density contrast is
+// formed from it by the exact subtraction of the mean (the forward z pass),
+// and near-empty nodes keep their full relative precision (no sum starting
+// from -1), which is what the FP64 path of the Q stencil reads there.
 #include "internal.h"
 
 namespace fdm {
@@ -41,11 +51,16 @@ __device__ __forceinline__ float spline_slope(float q) {
   return -6.0f * t * t;
 }
 
+// Integer units of one kernel value w (cells^-3 per unit particle mass).
+__device__ __forceinline__ unsigned long long spline_units(float w) {
+  return (unsigned long long)__double2ll_rn((double)w * 0x1p40);
+}
+
 template <int LOGN, bool FIXED>
 __global__ void __launch_bounds__(kBlock) k_spline_deposit(const void* __restrict__ pos,
                                                            int64_t np, float h, float inv_h,
                                                            float coef, int lo, int hi,
-                                                           float* __restrict__ rho) {
+                                                           unsigned long long* __restrict__ mass) {
   constexpr int N = 1 << LOGN;
   constexpr int MASK = N - 1;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -71,7 +86,7 @@ __global__ void __launch_bounds__(kBlock) k_spline_deposit(const void* __restric
           const float r2 = dxy2 + dz * dz;
           if (r2 > h2) continue;
           const float q = sqrtf(r2) * inv_h;
-          unsafeAtomicAdd(&rho[rxy + ((iz + oz) & MASK)], coef * spline_shape(q));
+          atomicAdd(&mass[rxy + ((iz + oz) & MASK)], spline_units(coef * spline_shape(q)));
         }
       }
     }
@@ -82,30 +97,34 @@ __global__ void __launch_bounds__(kBlock) k_spline_deposit(const void* __restric
 // kernel values of its particles into an LDS window covering every node the
 // tile's particles reach (offsets lo .. hi from the tile), then adds the
 // window's non-zero nodes to the mesh; particles that left their tile add to
-// the mesh directly.  Dense clumps then meet in LDS instead of in L2.
-// Windows up to a reach of kSplineReach cells on each side.
+// the mesh directly.  Dense clumps then meet in LDS instead of in L2.  The
+// window (64-bit integers) is sized at launch to the kernel's reach, up to
+// kSplineReach cells on each side.
 constexpr int kSplineReach = 5;
+constexpr int kSplineBlock = 512;
+template <int LOGN>
+__host__ __device__ constexpr int spline_tile_nodes(int span) {
+  return ((1 << tile_lx(LOGN)) + span) * ((1 << tile_ly(LOGN)) + span) *
+         ((1 << tile_lz(LOGN)) + span);
+}
 template <int LOGN, bool FIXED>
-__global__ void __launch_bounds__(kBlock) k_spline_deposit_tiled(const void* __restrict__ pos,
-                                                                 int64_t np, TileMap tm,
-                                                                 float h, float inv_h,
-                                                                 float coef, int lo, int hi,
-                                                                 float* __restrict__ rho) {
+__global__ void __launch_bounds__(kSplineBlock) k_spline_deposit_tiled(
+    const void* __restrict__ pos, int64_t np, TileMap tm, float h, float inv_h, float coef,
+    int lo, int hi, unsigned long long* __restrict__ mass) {
   constexpr int N = 1 << LOGN;
   constexpr int MASK = N - 1;
   constexpr int TX = 1 << tile_lx(LOGN), TY = 1 << tile_ly(LOGN), TZ = 1 << tile_lz(LOGN);
   constexpr int NTY = N / TY, NTZ = N / TZ;
-  constexpr int MW = (TX + 2 * kSplineReach) * (TY + 2 * kSplineReach) * (TZ + 2 * kSplineReach);
-  __shared__ float win[MW];
+  extern __shared__ unsigned long long win[];
   int t;
   unsigned p0, p1;
   if (!chunk_of(tm, t, p0, p1)) return;
   const int ox = (t / (NTY * NTZ)) * TX, oy = ((t / NTZ) % NTY) * TY, oz = (t % NTZ) * TZ;
   const int WX = TX + hi - lo, WY = TY + hi - lo, WZ = TZ + hi - lo;
-  for (int c = threadIdx.x; c < WX * WY * WZ; c += kBlock) win[c] = 0.0f;
+  for (int c = threadIdx.x; c < WX * WY * WZ; c += kSplineBlock) win[c] = 0ull;
   __syncthreads();
   const float h2 = h * h;
-  for (unsigned p = p0 + threadIdx.x; p < p1; p += kBlock) {
+  for (unsigned p = p0 + threadIdx.x; p < p1; p += kSplineBlock) {
     int ix, iy, iz;
     float fx, fy, fz;
     cell_frac<LOGN, FIXED>(pos, p, ix, fx);
@@ -125,25 +144,25 @@ __global__ void __launch_bounds__(kBlock) k_spline_deposit_tiled(const void* __r
           const float dz = (float)c - fz;
           const float r2 = dxy2 + dz * dz;
           if (r2 > h2) continue;
-          const float w = coef * spline_shape(sqrtf(r2) * inv_h);
+          const unsigned long long w = spline_units(coef * spline_shape(sqrtf(r2) * inv_h));
           if (inside)
             atomicAdd(&win[((rx + a - lo) * WY + (ry + b - lo)) * WZ + (rz + c - lo)], w);
           else
-            unsafeAtomicAdd(&rho[(((size_t)((ix + a) & MASK) * N) + ((iy + b) & MASK)) * N +
-                                 ((iz + c) & MASK)],
-                            w);
+            atomicAdd(&mass[(((size_t)((ix + a) & MASK) * N) + ((iy + b) & MASK)) * N +
+                            ((iz + c) & MASK)],
+                      w);
         }
       }
     }
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < WX * WY * WZ; c += kBlock) {
-    const float v = win[c];
-    if (v != 0.0f) {
+  for (int c = threadIdx.x; c < WX * WY * WZ; c += kSplineBlock) {
+    const unsigned long long v = win[c];
+    if (v != 0ull) {
       const int lx = c / (WY * WZ), ly = (c / WZ) % WY, lz = c % WZ;
       const size_t cell = ((size_t)((ox + lo + lx) & MASK) * N + ((oy + lo + ly) & MASK)) * N +
                           ((oz + lo + lz) & MASK);
-      unsafeAtomicAdd(&rho[cell], v);
+      atomicAdd(&mass[cell], v);
     }
   }
 }
@@ -228,12 +247,6 @@ __global__ void __launch_bounds__(kBlock) k_spline_drift(void* __restrict__ pos,
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_fill_value(float* __restrict__ p, size_t n,
-                                                       float v) {
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
-}
-
 unsigned spline_grid(int64_t n) {
   int64_t b = (n + kBlock - 1) / kBlock;
   if (b > 65536) b = 65536;
@@ -251,24 +264,28 @@ void spline_range(float h, int& lo, int& hi) {
 }  // namespace
 
 hipError_t launch_spline_deposit(bool fixed, int logn, const void* pos, int64_t np, float h,
-                                 float mass_per_mean, const TileMap* tm, float* delta,
-                                 hipStream_t s) {
-  const size_t ncell = (size_t)1 << (3 * logn);
-  hipLaunchKernelGGL(k_fill_value, dim3(spline_grid((int64_t)ncell)), dim3(kBlock), 0, s, delta,
-                     ncell, -1.0f);
+                                 const TileMap* tm, unsigned long long* mass, hipStream_t s) {
   int lo, hi;
   spline_range(h, lo, hi);
-  const float coef = (float)(8.0 / (M_PI * (double)h * h * h)) * mass_per_mean;
+  const float coef = (float)(8.0 / (M_PI * (double)h * h * h));
   // the window of a tile holds offsets lo .. hi beyond its cells
   if (tm && -lo <= kSplineReach && hi <= kSplineReach) {
     const dim3 gt(tiled_grid(np, tm->tiles));
-#define T_(LN)                                                                              \
-  if (fixed)                                                                                \
-    hipLaunchKernelGGL((k_spline_deposit_tiled<LN, true>), gt, dim3(kBlock), 0, s, pos, np, *tm, \
-                       h, 1.0f / h, coef, lo, hi, delta);                                   \
-  else                                                                                      \
-    hipLaunchKernelGGL((k_spline_deposit_tiled<LN, false>), gt, dim3(kBlock), 0, s, pos, np,    \
-                       *tm, h, 1.0f / h, coef, lo, hi, delta);
+#define T_(LN)                                                                                \
+  {                                                                                           \
+    /* windows above 64 KiB of LDS (h >= 3.5) need the launch limit raised */                \
+    const int lds = 8 * spline_tile_nodes<LN>(hi - lo);                                       \
+    const void* kf = fixed ? reinterpret_cast<const void*>(&k_spline_deposit_tiled<LN, true>)  \
+                           : reinterpret_cast<const void*>(&k_spline_deposit_tiled<LN, false>); \
+    const hipError_t e = hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, lds); \
+    if (e != hipSuccess) return e;                                                            \
+    if (fixed)                                                                                \
+      hipLaunchKernelGGL((k_spline_deposit_tiled<LN, true>), gt, dim3(kSplineBlock), lds, s,  \
+                         pos, np, *tm, h, 1.0f / h, coef, lo, hi, mass);                      \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_spline_deposit_tiled<LN, false>), gt, dim3(kSplineBlock), lds, s, \
+                         pos, np, *tm, h, 1.0f / h, coef, lo, hi, mass);                      \
+  }
     FDM_LOGN_SWITCH(logn, T_)
 #undef T_
     return hipGetLastError();
@@ -277,14 +294,15 @@ hipError_t launch_spline_deposit(bool fixed, int logn, const void* pos, int64_t 
 #define L_(LN)                                                                               \
   if (fixed)                                                                                 \
     hipLaunchKernelGGL((k_spline_deposit<LN, true>), dim3(g), dim3(kBlock), 0, s, pos, np, h, \
-                       1.0f / h, coef, lo, hi, delta);                                       \
+                       1.0f / h, coef, lo, hi, mass);                                        \
   else                                                                                       \
     hipLaunchKernelGGL((k_spline_deposit<LN, false>), dim3(g), dim3(kBlock), 0, s, pos, np, h, \
-                       1.0f / h, coef, lo, hi, delta);
+                       1.0f / h, coef, lo, hi, mass);
   FDM_LOGN_SWITCH(logn, L_)
 #undef L_
   return hipGetLastError();
 }
+
 
 hipError_t launch_spline_qforce(bool fixed, int logn, const void* pos, int64_t np,
                                 const float* q, float h, float* acc, hipStream_t s) {

@@ -144,12 +144,19 @@ __global__ void __launch_bounds__(kBlock) k_qpot(const float* __restrict__ delta
 // QX consecutive x-planes.  Each plane of s-values (with a one-cell y/z halo)
 // is loaded once into LDS; the x-neighbours stay in registers, so delta is
 // read about (QY+2)(QZ+2)/(QY QZ) times instead of once per stencil point.
-// The loads of plane x + 2 are issued before plane x is computed.
-constexpr int QY = 8, QZ = 32, QX = 16;
+// The loads of planes x + 2 and x + 3 are in flight while plane x is computed.
+#ifndef FDM_QPOT_QX
+#define FDM_QPOT_QX 16
+#endif
+#ifndef FDM_QPOT_QY
+#define FDM_QPOT_QY 16   // 256^3: 52.2 us against 55.4 with 8 rows (y-halo 1.19x against 1.33x)
+#endif
+constexpr int QY = FDM_QPOT_QY, QZ = 32, QX = FDM_QPOT_QX;
+constexpr int kQBlock = QY * QZ;   // threads per block of the tiled stencil
 #ifndef FDM_XCD_QPOT
 #define FDM_XCD_QPOT 8   // a z-row of blocks per XCD at a time (256^3: 64 -> 62 us)
 #endif
-static_assert(QY * QZ == kBlock, "one cell per thread and plane");
+static_assert(kQBlock % 64 == 0, "whole waves");
 
 template <bool FIXED>
 __device__ __forceinline__ float s_of(float d, const QConst& qc) {
@@ -159,7 +166,7 @@ __device__ __forceinline__ float s_of(float d, const QConst& qc) {
 }
 
 template <int LOGN, bool FIXED, int OUT>
-__global__ void __launch_bounds__(kBlock) k_qpot_tiled(const float* __restrict__ delta,
+__global__ void __launch_bounds__(kQBlock) k_qpot_tiled(const float* __restrict__ delta,
                                                        const long long* __restrict__ mass,
                                                        const float* __restrict__ phi,
                                                        float* __restrict__ q, QConst qc,
@@ -181,9 +188,10 @@ __global__ void __launch_bounds__(kBlock) k_qpot_tiled(const float* __restrict__
   constexpr int N = 1 << LOGN;
   constexpr int MASK = N - 1;
   constexpr int PY = QY + 2, PZ = QZ + 2;
-  constexpr int PER = (PY * PZ + kBlock - 1) / kBlock;   // plane values per thread
+  constexpr int PER = (PY * PZ + kQBlock - 1) / kQBlock;   // plane values per thread
   // two plane buffers: plane x + 1 is committed to one while plane x is read
-  // from the other, and plane x + 2 is already in flight in registers
+  // from the other, and planes x + 2 and x + 3 are already in flight in
+  // registers
   __shared__ float pl[2][PY * PZ];
   // FP64 sqrt(R) of one plane from the exact integer mass, built only where
   // this plane or the next holds a near-empty cell, so the in-plane values of
@@ -191,7 +199,7 @@ __global__ void __launch_bounds__(kBlock) k_qpot_tiled(const float* __restrict__
   __shared__ double dpl[FIXED ? PY * PZ : 1];
   // per wave: whether the committed plane holds a near-empty cell (two slots,
   // alternating by plane)
-  __shared__ uint32_t nflag[2][kBlock / 64];
+  __shared__ uint32_t nflag[2][kQBlock / 64];
   const int nby = N / QY, nbz = N / QZ;
   const int b = (int)xcd_block(blockIdx.x, gridDim.x, FDM_XCD_QPOT);
   const int bz = b % nbz, by = (b / nbz) % nby, bx = b / (nbz * nby);
@@ -201,25 +209,28 @@ __global__ void __launch_bounds__(kBlock) k_qpot_tiled(const float* __restrict__
   const float sq_floor = sqrtf((float)qc.fp64_below) - 1.0f;
   const float near = sq_floor + 1e-6f;            // s below which a cell takes the FP64 path
   const bool use64 = FIXED && qc.fp64_below > 0.0;
-  float pre[PER];
   auto plane_index = [&](int x, int c) {
     const int ly = c / PZ, lz = c % PZ;
     return (size_t)(x & MASK) * N * N + (size_t)((y0 - 1 + ly) & MASK) * N +
            ((z0 - 1 + lz) & MASK);
   };
-  auto fetch = [&](int x) {
+  // Two register buffers take alternate planes (even and odd offsets from
+  // x0), so while plane x is computed the loads of planes x + 2 and x + 3 are
+  // both in flight (twice the bytes in flight of one buffer).
+  float preA[PER], preB[PER];
+  auto fetch = [&](int x, float (&pre)[PER]) {
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-      const int c = threadIdx.x + k * kBlock;
+      const int c = threadIdx.x + k * kQBlock;
       if (c < PY * PZ) pre[k] = delta[plane_index(x, c)];
     }
   };
   // s-values of the fetched plane into buf; records whether any is near empty
-  auto commit = [&](float* buf, int slot) {
+  auto commit = [&](float* buf, int slot, const float (&pre)[PER]) {
     bool any = false;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-      const int c = threadIdx.x + k * kBlock;
+      const int c = threadIdx.x + k * kQBlock;
       if (c < PY * PZ) {
         const float sv = s_of<FIXED>(pre[k], qc);
         buf[c] = sv;
@@ -236,7 +247,7 @@ __global__ void __launch_bounds__(kBlock) k_qpot_tiled(const float* __restrict__
     if (!use64) return false;
     uint32_t f = 0;
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) f |= nflag[slot][w];
+    for (int w = 0; w < kQBlock / 64; ++w) f |= nflag[slot][w];
     return f != 0;
   };
   auto sd = [&](size_t j) {
@@ -248,28 +259,33 @@ __global__ void __launch_bounds__(kBlock) k_qpot_tiled(const float* __restrict__
   auto inplane = [&](const float* buf) {
     return (buf[cc - PZ] + buf[cc + PZ]) + (buf[cc - 1] + buf[cc + 1]);
   };
+  auto phi_at = [&](int x) { return phi[((size_t)x * N + y) * N + z]; };
   double wsum = 0.0, usum = 0.0;
   float s_prev = s_of<FIXED>(delta[((size_t)((x0 - 1) & MASK) * N + y) * N + z], qc);
-  // phi of the own column, loaded one plane ahead (psi and energy outputs)
-  float phi_cur = 0.0f;
-  if constexpr (OUT != kOutQ) phi_cur = phi[((size_t)x0 * N + y) * N + z];
-  fetch(x0);
-  commit(pl[0], 0);
-  fetch(x0 + 1);
+  // phi of the own column, two planes ahead (psi and energy outputs), in the
+  // slot of the plane's parity
+  float phA = 0.0f, phB = 0.0f;
+  if constexpr (OUT != kOutQ) {
+    phA = phi_at(x0);
+    phB = phi_at(x0 + 1);
+  }
+  fetch(x0, preA);
+  commit(pl[0], 0, preA);
+  fetch(x0 + 1, preB);
+  fetch(x0 + 2, preA);
   __syncthreads();
   bool near_cur = plane_near(0);                  // plane x holds a near-empty cell
   float s_cur = pl[0][cc];
   float in_cur = inplane(pl[0]);
   float sy_cur = pl[0][cc + PZ], sz_cur = pl[0][cc + 1];
   double d_prev = 0.0;                            // FP64 sqrt(R) of plane x - 1, own column
-  for (int x = x0; x < x0 + QX; ++x) {
+  // plane x: its successor x + 1 sits in `nxt` (loads issued two planes ago),
+  // which then takes plane x + 3; `ph` holds phi of plane x and then x + 2
+  auto plane = [&](int x, float (&nxt)[PER], float& ph) {
     const int nbi = (x - x0 + 1) & 1;
     float* nb = pl[nbi];
-    commit(nb, nbi);                          // plane x + 1
-    if (x + 2 <= x0 + QX) fetch(x + 2);
-    float phi_next = 0.0f;
-    if constexpr (OUT != kOutQ)
-      if (x + 1 < x0 + QX) phi_next = phi[((size_t)(x + 1) * N + y) * N + z];
+    commit(nb, nbi, nxt);                     // plane x + 1
+    if (x + 3 <= x0 + QX) fetch(x + 3, nxt);
     __syncthreads();
     const bool near_next = plane_near(nbi);
     const float s_next = nb[cc];
@@ -282,7 +298,7 @@ __global__ void __launch_bounds__(kBlock) k_qpot_tiled(const float* __restrict__
       if (near_cur || near_next) {
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
-          const int c = threadIdx.x + k * kBlock;
+          const int c = threadIdx.x + k * kQBlock;
           if (c < PY * PZ) dpl[c] = sd(plane_index(x, c));
         }
         __syncthreads();
@@ -312,15 +328,17 @@ __global__ void __launch_bounds__(kBlock) k_qpot_tiled(const float* __restrict__
       qv = qc.coef * lap / s_cur;
     }
     if constexpr (OUT == kOutPsi)
-      q[i] = fmaf(qc.psi_q, qv, qc.psi_g * phi_cur);
+      q[i] = fmaf(qc.psi_q, qv, qc.psi_g * ph);
     else
       q[i] = qv;
     if constexpr (OUT == kOutEnergy) {
-      wsum += (double)delta[i] * (double)phi_cur;
+      wsum += (double)delta[i] * (double)ph;
       const double e0 = (double)(s_next - s_cur), e1 = (double)(sy_cur - s_cur),
                    e2 = (double)(sz_cur - s_cur);
       usum += e0 * e0 + e1 * e1 + e2 * e2;
     }
+    if constexpr (OUT != kOutQ)
+      if (x + 2 < x0 + QX) ph = phi_at(x + 2);
     s_prev = s_cur;
     s_cur = s_next;
     in_cur = in_next;
@@ -328,10 +346,14 @@ __global__ void __launch_bounds__(kBlock) k_qpot_tiled(const float* __restrict__
     sz_cur = sz_next;
     d_prev = d_c;
     near_cur = near_next;
-    phi_cur = phi_next;
+  };
+  static_assert(QX % 2 == 0, "planes go in pairs");
+  for (int x = x0; x < x0 + QX; x += 2) {
+    plane(x, preB, phA);
+    plane(x + 1, preA, phB);
   }
   if constexpr (OUT == kOutEnergy) {
-    __shared__ double red[kBlock / 64];
+    __shared__ double red[kQBlock / 64];
     const double ws = block_sum(wsum, red);
     const double us = block_sum(usum, red);
     if (threadIdx.x == 0) {
@@ -353,16 +375,16 @@ hipError_t launch_qpot(int logn, bool fixed, int out, const float* delta,
                        double* partials, hipStream_t s, const Batch& bt) {
   const dim3 g((unsigned)qpot_blocks(logn), bt.count);
   if (out != kOutQ && out != kOutEnergy && out != kOutPsi) return hipErrorInvalidValue;
-#define K_(KERNEL, LN, FX)                                                                   \
+#define K_(KERNEL, LN, FX, TB)                                                               \
   {                                                                                          \
     if (out == kOutEnergy)                                                                   \
-      hipLaunchKernelGGL((KERNEL<LN, FX, kOutEnergy>), g, dim3(kBlock), 0, s, delta, mass,    \
+      hipLaunchKernelGGL((KERNEL<LN, FX, kOutEnergy>), g, dim3(TB), 0, s, delta, mass,        \
                          phi, q, qc, partials, bt);                                          \
     else if (out == kOutPsi)                                                                 \
-      hipLaunchKernelGGL((KERNEL<LN, FX, kOutPsi>), g, dim3(kBlock), 0, s, delta, mass, phi,  \
+      hipLaunchKernelGGL((KERNEL<LN, FX, kOutPsi>), g, dim3(TB), 0, s, delta, mass, phi,      \
                          q, qc, partials, bt);                                               \
     else                                                                                     \
-      hipLaunchKernelGGL((KERNEL<LN, FX, kOutQ>), g, dim3(kBlock), 0, s, delta, mass, phi, q, \
+      hipLaunchKernelGGL((KERNEL<LN, FX, kOutQ>), g, dim3(TB), 0, s, delta, mass, phi, q,     \
                          qc, partials, bt);                                                  \
   }
 #ifndef FDM_QPOT_SIMPLE
@@ -370,9 +392,9 @@ hipError_t launch_qpot(int logn, bool fixed, int out, const float* delta,
 #define T_(LN)                          \
   {                                     \
     if (fixed)                          \
-      K_(k_qpot_tiled, LN, true)        \
+      K_(k_qpot_tiled, LN, true, kQBlock)  \
     else                                \
-      K_(k_qpot_tiled, LN, false)       \
+      K_(k_qpot_tiled, LN, false, kQBlock) \
   }
     switch (logn) {
       case 5: T_(5); break;
@@ -389,9 +411,9 @@ hipError_t launch_qpot(int logn, bool fixed, int out, const float* delta,
 #define L_(LN)                   \
   {                              \
     if (fixed)                   \
-      K_(k_qpot, LN, true)       \
+      K_(k_qpot, LN, true, kBlock)  \
     else                         \
-      K_(k_qpot, LN, false)      \
+      K_(k_qpot, LN, false, kBlock) \
   }
   FDM_LOGN_SWITCH(logn, L_)
 #undef L_
@@ -427,6 +449,43 @@ hipError_t launch_reduce(const double* partials, int nblocks, int ncomp, double*
                          hipStream_t s, const Batch& bt) {
   hipLaunchKernelGGL(k_reduce, dim3(1, bt.count), dim3(kBlock), 0, s, partials, nblocks, ncomp,
                      out, bt);
+  return hipGetLastError();
+}
+
+// One synchronised state's energies from the stencil's interleaved
+// (delta phi, gradient) block partials and the gather's |p|^2 block partials:
+// each component summed in a fixed order (strided per thread, then a tree).
+__global__ void __launch_bounds__(kBlock) k_energy_row(const double* __restrict__ qpart, int nq,
+                                                       const double* __restrict__ kpart, int nk,
+                                                       EnergyScale sc, double* __restrict__ out) {
+  __shared__ double red[3][kBlock];
+  double w = 0.0, u = 0.0, k = 0.0;
+  for (int b = threadIdx.x; b < nq; b += kBlock) {
+    w += qpart[2 * (size_t)b];
+    u += qpart[2 * (size_t)b + 1];
+  }
+  for (int b = threadIdx.x; b < nk; b += kBlock) k += kpart[b];
+  red[0][threadIdx.x] = k;
+  red[1][threadIdx.x] = w;
+  red[2][threadIdx.x] = u;
+  __syncthreads();
+  for (int h = kBlock / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h)
+      for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double K = sc.k * red[0][0], W = sc.w * red[1][0], U = sc.u * red[2][0];
+    out[0] = K;
+    out[1] = W;
+    out[2] = U;
+    out[3] = K + W + U;
+  }
+}
+
+hipError_t launch_energy_row(const double* qpart, int nq, const double* kpart, int nk,
+                             EnergyScale sc, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_energy_row, dim3(1), dim3(kBlock), 0, s, qpart, nq, kpart, nk, sc, out);
   return hipGetLastError();
 }
 

@@ -269,7 +269,7 @@ class GpuExecutor:
     def __init__(self, device="cuda:0", batch_max_n: int = 64, pool_slots=None,
                  budget_bytes: int | None = None, max_large: int = 4, inflight: int = 2,
                  sort_every: int = 10, precision: int | None = None, keep_results: bool = False,
-                 vmax_safety: float = 2.0):
+                 vmax_safety: float = 2.0, graphs: bool = True):
         import torch
 
         from . import _lib as pm
@@ -289,6 +289,8 @@ class GpuExecutor:
         self.sort_every = sort_every
         self.keep_results = keep_results
         self.vmax_safety = vmax_safety
+        # pool calls are captured in HIP graphs and replayed (PM_BATCH_GRAPH)
+        self.graphs = graphs
         self.upload_stream = torch.cuda.Stream(self.device)
         self.copy_stream = torch.cuda.Stream(self.device)
         self.free_streams = []
@@ -443,7 +445,8 @@ class GpuExecutor:
                 for (started, kk), runs in groups.items():
                     pool["batch"].step([r["slot"] for r in runs],
                                        [r["times"][r["k"]: r["k"] + kk + 1] for r in runs],
-                                       self._flags(started))
+                                       self._flags(started) |
+                                       (self.pm.PM_BATCH_GRAPH if self.graphs else 0))
                     for r in runs:
                         r["k"] += kk
                         r["started"] = True
@@ -753,17 +756,20 @@ def serve_trace(trace, ics, executor, time_scale=1.0, chunk=10):
     return results, summarize(results, trace)
 
 
-def run_modes(trace, ics, scales=(1.0, 10.0, 100.0), serial=True, chunk=10, emit=print):
-    """Serve the trace batched at each time compression, then (optionally)
-    one request at a time in fixed point and in plain FP32 with all requests
-    queued at once; ``emit`` receives one summary dict per mode."""
+def run_modes(trace, ics, scales=(1.0, 10.0, 100.0), serial=True, chunk=10, emit=print,
+              eager=False):
+    """Serve the trace batched at each time compression (pool calls replayed
+    from HIP graphs; with ``eager`` also launched call by call), then
+    (optionally) one request at a time in fixed point and in plain FP32 with
+    all requests queued at once; ``emit`` receives one summary dict per mode."""
     out = []
     for scale in scales:
-        ex = GpuExecutor()
-        _, summ = serve_trace(trace, ics, ex, scale, chunk)
-        ex.close()
-        out.append({"mode": "batched", "time_scale": scale, **summ})
-        emit(out[-1])
+        for mode, graphs in (("batched", True), ("batched_eager", False))[:2 if eager else 1]:
+            ex = GpuExecutor(graphs=graphs)
+            _, summ = serve_trace(trace, ics, ex, scale, chunk)
+            ex.close()
+            out.append({"mode": mode, "time_scale": scale, **summ})
+            emit(out[-1])
     if serial:
         from ._lib import PM_FP32
         for name, states, prec in (("serial_fixed", ics, None),

@@ -66,8 +66,11 @@ def test_workspace_bytes(lib):
         # (key, rank, position/velocity/id copies: 36 B per particle), tables
         need = 8 * cells + 12 * cells + 8 * (n // 2 + 1) * n * n + 36 * npart
         assert b >= need
-        # plus energy partials and the sort's sliced tile counters and prefix sums
-        assert b < need + 8 * 2 * cells // 256 + cells // 8 + 65536
+        # plus energy partials (stencil blocks, and one |p|^2 partial per
+        # gather block: at most 65536 unsorted or one per tile chunk) and the
+        # sort's sliced tile counters and prefix sums
+        kpart = 8 * max(65536, cells // 1024 + npart // 8192 + 1)
+        assert b < need + 8 * 2 * cells // 256 + kpart + cells // 8 + 65536
         assert b % 256 == 0
 
 

@@ -1,0 +1,133 @@
+"""Energies recorded inside the step (pm_step_energies) against the oracle.
+
+K (Eq. (8)), W (gravitational potential energy) and U (K_rho of Eq. (6),
+forward differences of Eq. (11)'s mesh sum) at every synchronised time of a
+call, formed from the partial sums of the step's own stencil and gather,
+must match oracle.energies of the oracle's own states along the same
+schedule (relative 1e-5, the step's tolerance); the trajectory must stay
+that of pm_step.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import sine_mode_state, zeldovich_state
+
+from gpu_helpers import (cosmo_setup, periodic_diff, positions_cells, rel_l2, single_mode_setup,
+                         to_device)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pm(gpu):
+    import paper_1608_00802_amd as pm_mod
+    pm_mod.load_library()
+    return pm_mod
+
+
+def _oracle_series(x, v, op, times):
+    out = [oracle.energies(x, v, op, times[0] if op.comoving else 1.0)]
+    acc = None
+    for t0, t1 in zip(times[:-1], times[1:]):
+        x, v, acc = oracle.kdk_step(x, v, op, t0, t1, acc)
+        out.append(oracle.energies(x, v, op, t1 if op.comoving else 1.0))
+    return out, x, v
+
+
+def _compare(rows, ref, tol, label):
+    worst = 0.0
+    for s, (r, e) in enumerate(zip(rows, ref)):
+        scale = abs(e["K"]) + abs(e["W"]) + abs(e["U"])
+        for j, k in enumerate(("K", "W", "U")):
+            if e[k] != 0.0:
+                d = abs(r[j] - e[k]) / abs(e[k])
+                worst = max(worst, d)
+                assert d < tol, (label, s, k, r[j], e[k])
+        assert abs(r[3] - (r[0] + r[1] + r[2])) <= 1e-14 * scale
+        assert abs(r[3] - e["E"]) < tol * scale, (label, s, r[3], e["E"])
+    print(f"{label}: {len(rows)} rows, worst relative difference {worst:.2e}", flush=True)
+
+
+@pytest.mark.parametrize("sort", [0, 2])
+def test_step_energies_comoving_vs_oracle(pm, gpu, sort):
+    import torch
+    n = 64
+    box = 10.0 * n / 256
+    st = zeldovich_state(n, box, 0.05, seed=3, m_ev=1e-22)
+    lp, op = cosmo_setup(n, box, 1e-22)
+    ctx = pm.PMContext(lp, device=gpu)
+    pos, vel = to_device(st, gpu)
+    times = list(0.05 * np.exp(np.arange(9) * 0.02))
+    en = torch.full((len(times), 4), float("nan"), dtype=torch.float64, device=gpu)
+    flags = pm.PM_SORT_EVERY(sort) if sort else 0
+    ctx.step_energies(pos, vel, times, en, flags=flags)
+    torch.cuda.synchronize()
+    rows = en.cpu().numpy()
+    ref, xo, vo = _oracle_series(st.pos, st.vel, op, times)
+    _compare(rows, ref, 1e-5, f"comoving 64^3 sort every {sort}")
+    if sort == 0:
+        # the trajectory is the oracle's (and pm_step's) to the step tolerance
+        assert np.max(np.abs(periodic_diff(positions_cells(pos, n), xo, n))) < 1e-5
+        assert rel_l2(vel.cpu().numpy().T, vo) < 1e-5
+        c2 = pm.PMContext(lp, device=gpu)
+        p2, v2 = to_device(st, gpu)
+        c2.step(p2, v2, times)
+        torch.cuda.synchronize()
+        assert np.max(np.abs(periodic_diff(positions_cells(pos, n),
+                                           positions_cells(p2, n), n))) < 1e-6
+    # a continued call leaves row 0 alone and carries on
+    en2 = torch.full((3, 4), float("nan"), dtype=torch.float64, device=gpu)
+    t2 = [times[-1], times[-1] * 1.02, times[-1] * 1.02 ** 2]
+    ctx.step_energies(pos, vel, t2, en2, flags=flags | pm.PM_CONTINUE)
+    torch.cuda.synchronize()
+    r2 = en2.cpu().numpy()
+    assert np.all(np.isnan(r2[0])) and np.all(np.isfinite(r2[1:]))
+    ref2, _, _ = _oracle_series(xo, vo, op, t2)
+    _compare(r2[1:], ref2[1:], 1e-5, "continued call")
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_step_energies_static_single_mode(pm, gpu, precision):
+    """Static box of the single-mode problem: the rows follow the oracle's
+    energies (and E stays conserved to the scheme's second-order error)."""
+    import torch
+    st = sine_mode_state(32, 2, 2e-2)
+    lp, op = single_mode_setup(precision)
+    fp32 = precision == 0
+    ctx = pm.PMContext(lp, device=gpu)
+    pos, vel = to_device(st, gpu, fp32_positions=fp32)
+    times = list(np.arange(21) * 0.05)
+    en = torch.empty((len(times), 4), dtype=torch.float64, device=gpu)
+    ctx.step_energies(pos, vel, times, en)
+    torch.cuda.synchronize()
+    x0 = positions_cells(torch.from_numpy(st.pos_f32) if fp32 else
+                         torch.from_numpy(st.pos_fixed.view(np.int32)), 32, fp32)
+    ref, _, _ = _oracle_series(x0, st.vel, op, times)
+    # U is a sum of squared differences of sqrt(rho) of order 1e-4: the plain
+    # form's FP32 density carries 1e-7 absolute, i.e. 1e-3 relative there
+    _compare(en.cpu().numpy(), ref, 1e-5 if precision == 1 else 2e-3,
+             f"static single mode precision {precision}")
+
+
+def test_step_energies_cdm_and_bad_args(pm, gpu):
+    """Without quantum pressure U is zero; a null energy buffer is rejected."""
+    import torch
+    n = 32
+    st = zeldovich_state(n, 10.0, 0.1, seed=5, m_ev=None)
+    lp, op = cosmo_setup(n, 10.0, None)
+    ctx = pm.PMContext(lp, device=gpu)
+    pos, vel = to_device(st, gpu)
+    times = [0.1, 0.102, 0.104]
+    en = torch.empty((3, 4), dtype=torch.float64, device=gpu)
+    ctx.step_energies(pos, vel, times, en)
+    torch.cuda.synchronize()
+    rows = en.cpu().numpy()
+    assert np.all(rows[:, 2] == 0.0)
+    ref, _, _ = _oracle_series(st.pos, st.vel, op, times)
+    _compare(rows, ref, 1e-5, "CDM 32^3")
+    with pytest.raises(pm.PMError):
+        pm.pm_step_energies(ctx.ctx, ctx._pos(pos), ctx._vec(vel, "vel"), times, 0, 0)

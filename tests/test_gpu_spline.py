@@ -1,8 +1,10 @@
 """Parity of the spline-kernel steps (pm_spline_density, pm_spline_qforce;
 Sec. II A, Eqs. (9), (14), (15)) with the FP64 oracle, through the C ABI.
 
-Tolerances: the density is an FP32 atomic sum of about 180 kernel values per
-particle (relative rounding a few 1e-7): rel-L2 below 1e-5.  The force sums
+Tolerances: the density is an integer sum of about 180 kernel values per
+particle, each rounded once to 2^-40 of a particle after an FP32 evaluation
+(relative error a few 1e-7): rel-L2 below 1e-5, on near-empty nodes too, and
+the integer mesh is bitwise the same in every order and launch form.  The force sums
 about 180 terms Q_j grad W in float whose total is a small difference of
 large terms for smooth Q: rel-L2 below 1e-4.  The composed chain (density,
 then the library's Q from float delta, then the force) is held to 5e-4.
@@ -14,7 +16,7 @@ import pytest
 import oracle
 from synth import quantize_state
 
-from gpu_helpers import positions_cells, rel_l2
+from gpu_helpers import mass_mesh, positions_cells, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -179,6 +181,70 @@ def test_spline_rejects_bad_h(pm, gpu):
     ctx, _ = _setup(pm, gpu, n, st.npart, 1)
     pos = _positions(st, gpu, False)
     delta = torch.empty(n ** 3, dtype=torch.float32, device=gpu)
-    for h in (0.1, 8.0, float("nan")):
+    for h in (0.1, 1.5, 1.99, 8.0, float("nan")):
         with pytest.raises(pm.PMError):
             ctx.spline_density(pos, delta, h)
+    # the smallest accepted h: every particle deposits its mass to 0.2 %
+    ctx.spline_density(pos, delta, 2.0)
+    torch.cuda.synchronize()
+    total = mass_mesh(ctx).astype(np.float64).sum() / (st.npart * 2.0 ** 40)
+    assert abs(total - 1.0) < 2e-3
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_spline_density_bitwise_order_free(pm, gpu, precision):
+    """The integer spline density is bitwise the same on repeated calls, for a
+    permuted particle order and from the tiled (sorted) and direct forms."""
+    import torch
+    n = 32
+    st = _clumps(n, 30001, 11)
+    ctx, _ = _setup(pm, gpu, n, st.npart, precision)
+    fp32 = precision == 0
+    pos = _positions(st, gpu, fp32)
+    delta = torch.empty(n ** 3, dtype=torch.float32, device=gpu)
+    ctx.spline_density(pos, delta, 3.5)
+    m0 = mass_mesh(ctx).copy()
+    ctx.spline_density(pos, delta, 3.5)
+    assert np.array_equal(mass_mesh(ctx), m0)
+    perm = torch.from_numpy(np.random.default_rng(2).permutation(st.npart)).to(gpu)
+    ctx.spline_density(pos[:, perm].contiguous(), delta, 3.5)
+    assert np.array_equal(mass_mesh(ctx), m0)
+    ctx2, _ = _setup(pm, gpu, n, st.npart, precision)
+    p2 = pos.clone()
+    vel = torch.zeros(3, st.npart, dtype=torch.float32, device=gpu)
+    ctx2.sort(p2, vel)
+    ctx2.spline_density(p2, delta, 3.5)
+    assert np.array_equal(mass_mesh(ctx2), m0)
+
+
+@pytest.mark.parametrize("n,width", [(32, 1.2), (64, 2.0)])
+def test_spline_q_near_empty_nodes_fp64(pm, gpu, n, width):
+    """Q of the spline density in a box with voids (clumps, no background):
+    the fixed-point form takes Q from the integer density in FP64 on nodes
+    below 1e-3 of the mean; all, low and other nodes against the oracle."""
+    import torch
+    rng = np.random.default_rng(n)
+    c = rng.random((3, 3)) * n
+    npart = 40000
+    x = (c[rng.integers(0, 3, npart)] + width * rng.standard_normal((npart, 3))) % n
+    st = quantize_state(x, np.zeros((npart, 3)), n, {"kind": "voids"})
+    hm = 0.5
+    lp = pm.make_params(n, npart, float(n), four_pi_G_rhobar=1.0, hbar_over_m=hm,
+                        rho_floor=1e-6, rho_fp64_below=1e-3)
+    op = oracle.Params(n=n, box=float(n), S=1.0, hbar_m=hm, rho_floor=1e-6)
+    ctx = pm.PMContext(lp, device=gpu)
+    pos = _positions(st, gpu, False)
+    delta = torch.empty(n ** 3, dtype=torch.float32, device=gpu)
+    q = torch.empty(n ** 3, dtype=torch.float32, device=gpu)
+    ctx.spline_density(pos, delta, 3.5)
+    ctx.qpot(None, q)
+    torch.cuda.synchronize()
+    rho = oracle.spline_deposit(st.pos, op, 3.5)
+    ref = oracle.qpot(rho, op)
+    got = q.cpu().numpy().astype(np.float64).reshape(n, n, n)
+    low = (rho < 1e-3) & (rho > 0.0)
+    errs = (rel_l2(got, ref), rel_l2(got[low], ref[low]), rel_l2(got[~low], ref[~low]))
+    print(f"spline Q with voids {n}^3: {int(low.sum())} nodes in (0, 1e-3), "
+          f"{int((rho == 0).sum())} empty; rel-L2 all / low / other {errs}", flush=True)
+    assert low.sum() > 100
+    assert max(errs) < 1e-5

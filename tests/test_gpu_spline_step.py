@@ -116,3 +116,30 @@ def test_spline_step_conserves_the_discrete_energy(pm, gpu):
         torch.cuda.synchronize()
     assert errs[1] < 1e-3
     assert 3.0 < errs[0] / errs[1] < 5.5, errs
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_sorted_spline_steps_with_strays_vs_oracle(pm, gpu, precision):
+    """A context sorted first (tiled LDS deposit), then stepped with fast
+    particles (about half a cell per step) so that many leave their tile
+    windows: the deposit mixes tiled and direct additions; positions and
+    velocities against the oracle's spline leapfrog."""
+    import torch
+    n = 32
+    st = _jittered(n, 9)
+    rng = np.random.default_rng(10)
+    fp32 = precision == 0
+    lp = pm.make_params(n, n ** 3, float(n), precision=precision, four_pi_G_rhobar=1.0,
+                        hbar_over_m=0.8, rho_floor=1e-6, rho_fp64_below=1e-3)
+    op = oracle.Params(n=n, box=float(n), S=1.0, hbar_m=0.8, rho_floor=1e-6)
+    ctx = pm.PMContext(lp, device=gpu)
+    pos, vel = to_device(st, gpu, fp32_positions=fp32)
+    vel.copy_(torch.from_numpy((5.0 * rng.standard_normal((3, n ** 3))).astype(np.float32)))
+    ctx.sort(pos, vel)
+    torch.cuda.synchronize()
+    x0 = positions_cells(pos, n, fp32)
+    v0 = vel.cpu().numpy().T.astype(np.float64)
+    times = list(np.linspace(0.0, 0.8, 9))      # 0.1 per step: ~0.5 cell per step
+    ctx.spline_step(pos, vel, times, 3.5)
+    x, v = oracle.spline_run(x0, v0, op, times, 3.5)
+    _compare(pos, vel, x, v, n, fp32)
