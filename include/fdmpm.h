@@ -414,6 +414,23 @@ pm_status pm_batch_step(pm_batch* batch, void* d_pos, float* d_vel, int32_t nact
  * pinned staging buffers (the caller's workspace is untouched). */
 pm_status pm_batch_destroy(pm_batch* batch);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid it): the Poisson solve
+ * of pm_poisson without a context or workspace.  d_phi (float [N^3])
+ * receives phi with lap(phi) = S delta (S in 1/time^2, cell units: the S of
+ * pm_poisson), zero mean, from d_delta (float [N^3], its mean ignored), both
+ * C-order device arrays owned by the caller; enqueued on hip_stream (NULL =
+ * default stream).  The spectrum and the FFT's constant tables live in a
+ * device array of the library, one per GPU, held until the process ends:
+ * 8.5 MB, enough for N <= 128.  Calls that overlap on one GPU (concurrent
+ * streams, threads) share it and race; serialise them.  Nothing is cleared
+ * between calls (every pass writes all it reads).  PM_EINVAL for null
+ * pointers or a non-finite S, PM_EUNSUPPORTED for N not a power of two >= 16,
+ * PM_ENOMEM for N above 128 (the array's size), PM_EDEVICE for HIP errors.
+ * No hipMalloc, hipFree or allocating library call is made. */
+pm_status pm_poisson_static(int32_t n_mesh, double S, const float* d_delta, float* d_phi,
+                            void* hip_stream);
+
 /* Free the host-side context (no device memory is owned). */
 pm_status pm_destroy(pm_ctx* ctx);
 

@@ -31,8 +31,8 @@ EXPORTED = ("pm_workspace_bytes", "pm_init", "pm_deposit", "pm_poisson", "pm_qpo
             "pm_density_rms_diff", "pm_power_spectrum", "pm_spline_density",
             "pm_spline_qforce", "pm_spline_step", "pm_spline_energy", "pm_timing_enable", "pm_timing_read",
             "pm_batch_workspace_bytes", "pm_batch_init", "pm_batch_slot_offset",
-            "pm_batch_set_slot", "pm_batch_step", "pm_batch_destroy", "pm_destroy",
-            "pm_strerror")
+            "pm_batch_set_slot", "pm_batch_step", "pm_batch_destroy", "pm_poisson_static",
+            "pm_destroy", "pm_strerror")
 PM_BATCH_MAX_STEPS = 256
 
 
@@ -122,6 +122,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "pm_batch_step": ([c_void_p, c_void_p, c_void_p, c_int32, P(c_int32), P(c_double),
                            c_int32, c_int32], c_int32),
         "pm_batch_destroy": ([c_void_p], c_int32),
+        "pm_poisson_static": ([c_int32, c_double, c_void_p, c_void_p, c_void_p], c_int32),
         "pm_destroy": ([c_void_p], c_int32),
         "pm_strerror": ([c_int32], ctypes.c_char_p),
     }

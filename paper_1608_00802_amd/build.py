@@ -16,7 +16,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB_NAME = "libfdmpm.so"
-SOURCES = ["api.hip", "deposit.hip", "fft.hip", "stencil.hip", "gather.hip", "sort.hip", "diag.hip", "spline.hip"]
+SOURCES = ["api.hip", "deposit.hip", "fft.hip", "stencil.hip", "gather.hip", "sort.hip", "diag.hip",
+           "spline.hip", "noalloc.hip"]
 ARCH = "gfx950"
 
 COMMON_FLAGS = [
