@@ -51,6 +51,17 @@ __device__ __forceinline__ float spline_slope(float q) {
   return -6.0f * t * t;
 }
 
+// Offsets o in [lo, hi] along one axis that may satisfy (o - f)^2 <= rem,
+// rem being h^2 less the other axes' squared distances: the integers in
+// [f - sqrt(rem), f + sqrt(rem)], widened to the enclosing integers so that
+// rounding of the square root never drops a node; the exact test on r^2
+// inside the loops decides, so the nodes visited are those of the full cube.
+__device__ __forceinline__ void axis_span(float f, float rem, int lo, int hi, int& a, int& b) {
+  const float w = sqrtf(fmaxf(rem, 0.0f));
+  a = max(lo, (int)floorf(f - w));
+  b = min(hi, (int)ceilf(f + w));
+}
+
 // Integer units of one kernel value w (cells^-3 per unit particle mass).
 __device__ __forceinline__ unsigned long long spline_units(float w) {
   return (unsigned long long)__double2ll_rn((double)w * 0x1p40);
@@ -76,12 +87,16 @@ __global__ void __launch_bounds__(kBlock) k_spline_deposit(const void* __restric
       const float dx2 = dx * dx;
       if (dx2 > h2) continue;
       const size_t rx = (size_t)((ix + ox) & MASK) * N;
-      for (int oy = lo; oy <= hi; ++oy) {
+      int y0, y1;
+      axis_span(fy, h2 - dx2, lo, hi, y0, y1);
+      for (int oy = y0; oy <= y1; ++oy) {
         const float dy = (float)oy - fy;
         const float dxy2 = dx2 + dy * dy;
         if (dxy2 > h2) continue;
         const size_t rxy = (rx + ((iy + oy) & MASK)) * N;
-        for (int oz = lo; oz <= hi; ++oz) {
+        int z0, z1;
+        axis_span(fz, h2 - dxy2, lo, hi, z0, z1);
+        for (int oz = z0; oz <= z1; ++oz) {
           const float dz = (float)oz - fz;
           const float r2 = dxy2 + dz * dz;
           if (r2 > h2) continue;
@@ -136,11 +151,15 @@ __global__ void __launch_bounds__(kSplineBlock) k_spline_deposit_tiled(
       const float dx = (float)a - fx;
       const float dx2 = dx * dx;
       if (dx2 > h2) continue;
-      for (int b = lo; b <= hi; ++b) {
+      int b0, b1;
+      axis_span(fy, h2 - dx2, lo, hi, b0, b1);
+      for (int b = b0; b <= b1; ++b) {
         const float dy = (float)b - fy;
         const float dxy2 = dx2 + dy * dy;
         if (dxy2 > h2) continue;
-        for (int c = lo; c <= hi; ++c) {
+        int c0, c1;
+        axis_span(fz, h2 - dxy2, lo, hi, c0, c1);
+        for (int c = c0; c <= c1; ++c) {
           const float dz = (float)c - fz;
           const float r2 = dxy2 + dz * dz;
           if (r2 > h2) continue;
@@ -190,12 +209,16 @@ __global__ void __launch_bounds__(kBlock) k_spline_qforce(const void* __restrict
       const float dx2 = dx * dx;
       if (dx2 > h2) continue;
       const size_t rx = (size_t)((ix + ox) & MASK) * N;
-      for (int oy = lo; oy <= hi; ++oy) {
+      int y0, y1;
+      axis_span(fy, h2 - dx2, lo, hi, y0, y1);
+      for (int oy = y0; oy <= y1; ++oy) {
         const float dy = (float)oy - fy;
         const float dxy2 = dx2 + dy * dy;
         if (dxy2 > h2) continue;
         const size_t rxy = (rx + ((iy + oy) & MASK)) * N;
-        for (int oz = lo; oz <= hi; ++oz) {
+        int z0, z1;
+        axis_span(fz, h2 - dxy2, lo, hi, z0, z1);
+        for (int oz = z0; oz <= z1; ++oz) {
           const float dz = (float)oz - fz;
           const float r2 = dxy2 + dz * dz;
           if (r2 > h2 || r2 == 0.0f) continue;

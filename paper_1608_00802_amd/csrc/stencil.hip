@@ -149,7 +149,7 @@ __global__ void __launch_bounds__(kBlock) k_qpot(const float* __restrict__ delta
 #define FDM_QPOT_QX 16
 #endif
 #ifndef FDM_QPOT_QY
-#define FDM_QPOT_QY 16   // 256^3: 52.2 us against 55.4 with 8 rows (y-halo 1.19x against 1.33x)
+#define FDM_QPOT_QY 32   // 256^3: 51.1 us against 52.2 (16 rows) and 55.4 (8 rows)
 #endif
 constexpr int QY = FDM_QPOT_QY, QZ = 32, QX = FDM_QPOT_QX;
 constexpr int kQBlock = QY * QZ;   // threads per block of the tiled stencil
