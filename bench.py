@@ -9,11 +9,13 @@ mass 1e-22 eV, Omega_m = 0.3, h = 0.7, Zel'dovich initial conditions at
 a = 0.01 (seed 1), 32-bit fixed-point positions, FP32 FFT and stencils.
 Inputs are resident in HBM before the timed region.
 
-Prints one JSON line.  Also measured: the same box evolved to a = 0.5 (a
-nonlinear, clustered state), the plain FP32 form of the step, per-kernel
-times from HIP events on the library's stream, a short served trace of
-independent requests (batched and one at a time), and the FP64 oracle on
-the host as a CPU baseline.
+Prints one JSON line.  Also measured: the same step with the energies of
+every synchronised time formed inside its kernels, the same box evolved to
+a = 0.5 (a nonlinear, clustered state), the plain FP32 form of the step,
+per-kernel times from HIP events on the library's stream, a short served
+trace of independent requests (batched and one at a time), and the FP64
+oracle on the host as a CPU baseline (whose fields also give both forms'
+errors at the initial state).
 """
 
 from __future__ import annotations
@@ -77,7 +79,7 @@ EVOLVE_DLNA = math.log(100.0) / 150.0
 
 
 def run_gpu(st, n, steps, warmup, a_start, kernel_pass=True, sort_every=10, fp32=False,
-            evolve_to=None, box=10.0, diag=False):
+            evolve_to=None, box=10.0, diag=False, energies=False):
     """Time `steps` steps (after `warmup`) from a_start; with evolve_to, the
     state is first stepped (untimed) from a_start to evolve_to under the
     time-step condition of Sec. II A (no particle moves more than one cell
@@ -125,19 +127,31 @@ def run_gpu(st, n, steps, warmup, a_start, kernel_pass=True, sort_every=10, fp32
     stream = ctx.stream
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
+    # with energies: K, W, U, E of every synchronised time, formed inside the
+    # step's kernels (pm_step_energies), into a device array
+    rows = torch.empty((steps + 1, 4), dtype=torch.float64, device=dev) if energies else None
+
+    def timed_call(seg):
+        if energies:
+            ctx.step_energies(pos, vel, seg, rows, flags=pm.PM_CONTINUE | sort_flag)
+        else:
+            ctx.step(pos, vel, seg, flags=pm.PM_CONTINUE | sort_flag)
+
     t0 = time.perf_counter()
     ev0.record(stream)
-    ctx.step(pos, vel, times[warmup: warmup + steps + 1], flags=pm.PM_CONTINUE | sort_flag)
+    timed_call(times[warmup: warmup + steps + 1])
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ev_ms = ev0.elapsed_time(ev1)
     out = {"wall_s": wall, "event_ms": ev_ms, "np": st.npart, "evolve_steps": evolve_steps,
            "a_timed": a_start, "a_timed_end": times[warmup + steps]}
+    if energies:
+        r = rows.cpu().numpy()
+        out["energy_rows"] = {"first": [float(v) for v in r[1]], "last": [float(v) for v in r[-1]]}
     if kernel_pass:
         ctx.timing(True)
-        ctx.step(pos, vel, times[warmup + steps: warmup + 2 * steps + 1],
-                 flags=pm.PM_CONTINUE | sort_flag)
+        timed_call(times[warmup + steps: warmup + 2 * steps + 1])
         out["kernels"] = ctx.timing_read()
         ctx.timing(False)
     if diag:
@@ -260,13 +274,15 @@ def copy_calibration(nbytes=1 << 30, reps=3):
     torch.cuda.empty_cache()
 
 
-# rocprofv3 kernel-name prefix of each kernel family in the traffic summary
-# (inside a call the gather reads psi alone and the stencil writes psi)
-TRAFFIC_KERNEL = {"gather_kick_drift": "k_gather_tiled<8, true, false, 1, true, 0>",
-                  "deposit": "k_deposit_tiled<8, true>", "qpot": "k_qpot_tiled<8, true, 2>",
-                  "r2c_z": "k_r2c_z<8, 0>", "fft_y": "k_fft_y_reg<8, false>",
-                  "fft_x_green": "k_fft_x_green_reg<8>", "fft_y_inv": "k_fft_y_reg<8, true>",
-                  "c2r_z": "k_c2r_z<8>"}
+# rocprofv3 kernel name of each kernel family in the traffic summary, for
+# log2 N = {ln} (inside a call the gather reads psi alone and the stencil
+# writes psi)
+TRAFFIC_KERNEL = {"gather_kick_drift": "k_gather_tiled<{ln}, true, false, 1, true, 0, false>",
+                  "deposit": "k_deposit_tiled<{ln}, true>",
+                  "qpot": "k_qpot_tiled<{ln}, true, 2>", "r2c_z": "k_r2c_z<{ln}, 0>",
+                  "fft_y": "k_fft_y_reg<{ln}, false>", "fft_x_green": "k_fft_x_green_reg<{ln}>",
+                  "fft_y_inv": "k_fft_y_reg<{ln}, true>", "c2r_z": "k_c2r_z<{ln}>",
+                  "fill_zero": "k_fill_zero16"}
 
 
 # the sources each kernel family is built from (its counters go stale when one changes)
@@ -275,6 +291,7 @@ TRAFFIC_SOURCES = {"gather_kick_drift": ("gather.hip", "cic.h", "internal.h"),
                    "qpot": ("stencil.hip", "internal.h")}
 for _k in ("r2c_z", "fft_y", "fft_x_green", "fft_y_inv", "c2r_z"):
     TRAFFIC_SOURCES[_k] = ("fft.hip", "internal.h")
+TRAFFIC_SOURCES["fill_zero"] = ("deposit.hip", "internal.h")
 
 
 def measured_traffic(kernel: str, n: int):
@@ -294,7 +311,7 @@ def measured_traffic(kernel: str, n: int):
         src = os.path.join(ROOT, "paper_1608_00802_amd", "csrc", f)
         if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != h:
             return None
-    k = rec["kernels"].get(TRAFFIC_KERNEL[kernel])
+    k = rec["kernels"].get(TRAFFIC_KERNEL[kernel].format(ln=n.bit_length() - 1))
     if k is None:
         return None
     return int(k["fetch_bytes"] + k["write_bytes"])
@@ -394,6 +411,65 @@ def cpu_baseline(st, n, box, gpu_sets=None):
     return out
 
 
+def batch_launch_section(n=32, slots=64, steps=10, calls=6):
+    """Launch cost of batched small boxes: one batch of `slots` runs of n^3
+    (every kernel launched once for all slots) stepped `calls` times by
+    `steps` steps, call by call and replayed from captured HIP graphs
+    (PM_BATCH_GRAPH); ms per step of the whole batch, and the GPU time of the
+    kernels alone from HIP events around each call."""
+    import numpy as np
+    import torch
+
+    import paper_1608_00802_amd as pm
+    from paper_1608_00802_amd import serve
+    from synth import zeldovich_state
+
+    dev = torch.device("cuda:0")
+    out = {"batch": f"{slots} runs of {n}^3 particles on {n}^3 meshes, {steps} steps per call"}
+    states = [zeldovich_state(n, 2.0 + 0.1 * i, 0.01, seed=100 + i, m_ev=1e-22)
+              for i in range(slots)]
+    for mode, flag in (("eager", 0), ("graph", pm.PM_BATCH_GRAPH)):
+        stream = torch.cuda.Stream(dev)
+        lp = pm.make_params(n, n ** 3, 2.0, comoving=True, omega_m=0.3, omega_l=0.7, h0=1.0)
+        with torch.cuda.stream(stream):
+            b = pm.PMBatch(lp, slots, device=dev, stream=stream)
+        for i, st in enumerate(states):
+            box = 2.0 + 0.1 * i
+            hm = serve.hbar_over_m(1e-22)
+            b.load(i, torch.from_numpy(st.pos_fixed.view(np.int32).copy()).to(dev),
+                   torch.from_numpy(st.vel32.copy()).to(dev), box, hm)
+        sl = list(range(slots))
+        a = [0.01] * slots
+
+        def call(first):
+            times = []
+            for i in range(slots):
+                t = [a[i] * math.exp(k * DLNA) for k in range(steps + 1)]
+                a[i] = t[-1]
+                times.append(t)
+            b.step(sl, times, pm.PM_SORT_EVERY(10) | flag | (0 if first else pm.PM_CONTINUE))
+
+        call(True)
+        call(False)                       # captures the continued shape
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(calls):
+            call(False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[mode] = {"ms_per_step": round(wall * 1e3 / (calls * steps), 4),
+                     "event_ms_per_step": round(e0.elapsed_time(e1) / (calls * steps), 4),
+                     "particle_updates_per_s": slots * n ** 3 * calls * steps / wall}
+        b.close()
+    out["speedup_graph_vs_eager"] = round(out["eager"]["ms_per_step"] /
+                                          out["graph"]["ms_per_step"], 3)
+    return out
+
+
 def serve_section(trace, ics):
     """Served trace: batched at a compressed arrival rate, and one request at
     a time (fixed point, plain FP32) with every request queued at once."""
@@ -401,18 +477,22 @@ def serve_section(trace, ics):
     out = {"requests": len(trace), "trace": "Poisson arrivals (4/s, seed 2026) of independent "
            "runs: N in {32,64,128,256}, box U[1,10] Mpc/h, m log-uniform [1e-23,1e-21] eV, "
            "50-200 steps from a = 0.01, Zel'dovich ICs built on the host before the clock"}
-    for rec in serve.run_modes(trace, ics, scales=(100.0,), serial=True, emit=lambda d: None):
+    for rec in serve.run_modes(trace, ics, scales=(100.0,), serial=True, emit=lambda d: None,
+                               eager=True):
         rec = dict(rec)
         rec.pop("per_size", None)
         name = rec.pop("mode") + ("" if rec.get("time_scale") is None else "_x100")
         rec.pop("time_scale", None)
         out[name] = {k: (round(v, 5) if isinstance(v, float) else v) for k, v in rec.items()}
     b = out.get("batched_x100", {}).get("particle_updates_per_s")
+    be = out.get("batched_eager_x100", {}).get("particle_updates_per_s")
     s1 = out.get("serial_fixed", {}).get("particle_updates_per_s")
     s2 = out.get("serial_fp32", {}).get("particle_updates_per_s")
     if b and s1 and s2:
         out["speedup_batched_vs_serial_fixed"] = round(b / s1, 3)
         out["speedup_batched_vs_serial_fp32"] = round(b / s2, 3)
+    if b and be:
+        out["speedup_graphs_vs_eager_batched"] = round(b / be, 3)
     return out
 
 
@@ -426,12 +506,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-evolved", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-energies", action="store_true",
+                    help="skip the timed step with per-step energies")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-spline", action="store_true",
                     help="skip the step with the spline kernel")
     ap.add_argument("--no-diag", action="store_true",
                     help="skip the grid diagnostics after the evolved run")
     ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--evolved-only", action="store_true",
+                    help="profiling aid: time only the evolved (a = 0.5) state, print a short "
+                         "line instead of the benchmark line")
     ap.add_argument("--no-kernel-pass", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (counter calibration)")
@@ -457,6 +542,14 @@ def main():
         ics = serve.generate_ics(trace, workers)
     if args.copy_calibration:
         copy_calibration()
+    if args.evolved_only:
+        # profiling aid: only the evolved state's steps (no JSON line)
+        re_ = run_gpu(st, n, args.steps, args.warmup, 0.01, kernel_pass=not args.no_kernel_pass,
+                      sort_every=args.sort_every, evolve_to=0.5, box=args.box)
+        print(json.dumps({"evolved_only": True, "a": re_["a_timed"], "evolve_steps":
+                          re_["evolve_steps"], "ms_per_step": re_["wall_s"] * 1e3 / args.steps}),
+              flush=True)
+        return
     res = run_gpu(st, n, args.steps, args.warmup, 0.01, kernel_pass=not args.no_kernel_pass,
                   sort_every=args.sort_every, box=args.box)
     value = res["np"] * args.steps / res["wall_s"]
@@ -501,6 +594,18 @@ def main():
         step_bytes = sum(ab[k] for k in per_step)
         line["step_alg_bytes"] = step_bytes
         line["step_alg_GBs"] = round(step_bytes / (res["wall_s"] / args.steps) / 1e9, 1)
+    if not args.no_energies:
+        rn = run_gpu(st, n, args.steps, args.warmup, 0.01, kernel_pass=not args.no_kernel_pass,
+                     sort_every=args.sort_every, box=args.box, energies=True)
+        line["with_energies"] = {
+            "form": "pm_step_energies: the same step with K (gather, at the synchronised "
+                    "time), W and U (Q stencil) partial sums and one reduction kernel per step",
+            "value": rn["np"] * args.steps / rn["wall_s"],
+            "ms_per_step": rn["wall_s"] * 1e3 / args.steps,
+            "rows_K_W_U_E": rn["energy_rows"]}
+        if "kernels" in rn:
+            line["with_energies"]["kernels"] = kernel_table(rn["kernels"], n, rn["np"],
+                                                            args.steps)
     if not args.no_fp32:
         rf = run_gpu(st, n, args.steps, args.warmup, 0.01, kernel_pass=False,
                      sort_every=args.sort_every, fp32=True, box=args.box)
@@ -530,6 +635,8 @@ def main():
             line["evolved"]["diagnostics"] = re_["diag"]
     if not args.no_spline:
         line["spline_form"] = spline_section(st, n, args.box)
+    if not args.no_serve:
+        line["batch_launch"] = batch_launch_section()
     if trace is not None:
         line["serving"] = serve_section(trace, ics)
         del ics
