@@ -130,13 +130,21 @@ __device__ __forceinline__ void fft_rows(float2* __restrict__ buf, const float2*
 #define FDM_FFTZ_XG 4   // 512^3 (8 rows per block): C2R 374 -> 351 us
 #endif
 #ifndef FDM_FFT_Z_ELEMS_512
-// z-pass elements per block at N = 512: 16 rows, whole 128-byte lines of the
-// kz-major spectrum per row (C2R 352 -> 279 us, R2C 482 -> 436 us)
-#define FDM_FFT_Z_ELEMS_512 8192
+// z-pass elements per block at N = 512: 32 rows, two whole 128-byte lines of
+// the kz-major spectrum per kz (with 512 threads: C2R 263 -> 239 us against
+// 16 rows, R2C unchanged; 8 rows took 352 and 482 us)
+#define FDM_FFT_Z_ELEMS_512 16384
 #endif
 #ifndef FDM_FFT_Z_ELEMS
 #define FDM_FFT_Z_ELEMS 4096
 #endif
+#ifndef FDM_FFTZ_BLOCK
+// threads per block of the z passes (512 against 256: 256^3 R2C 64 -> 60 us,
+// 512^3 R2C 439 -> 428 us and C2R 279 -> 263 us with 16 rows; 1024 threads
+// with 32 rows: C2R 231 but R2C 476 us)
+#define FDM_FFTZ_BLOCK 512
+#endif
+constexpr int kZBlock = FDM_FFTZ_BLOCK;
 // Rows (complex elements / N) per block of the z passes.  Small tiles leave
 // room for four or more blocks per CU, so one block's transform overlaps
 // another's loads (256^3: 30 us less per step than tiles twice as large).
@@ -232,7 +240,7 @@ __device__ __forceinline__ void fft_first(float2 (&v)[F1], int n2, const float2*
 
 // ---------------------------------------------------------------- pass 1
 template <int LOGN, int SRC>
-__global__ void __launch_bounds__(kBlock) k_r2c_z(const void* __restrict__ in,
+__global__ void __launch_bounds__(kZBlock) k_r2c_z(const void* __restrict__ in,
                                                   float* __restrict__ delta_out,
                                                   float2* __restrict__ spec,
                                                   const float2* __restrict__ tw, DeltaConv conv,
@@ -253,17 +261,17 @@ __global__ void __launch_bounds__(kBlock) k_r2c_z(const void* __restrict__ in,
   const int zb = (int)xcd_block(blockIdx.x, gridDim.x, Tiles<N>::XG);
   const int x = zb / (N / TZ);
   const int y0 = (zb % (N / TZ)) * TZ;
-  for (int k = tid; k < N; k += kBlock) tws[k] = tw[k];
+  for (int k = tid; k < N; k += kZBlock) tws[k] = tw[k];
   {
     // all of a thread's loads are issued before the first is used
     constexpr int NE = TZ * H;
-    constexpr int PER = (NE + kBlock - 1) / kBlock;
+    constexpr int PER = (NE + kZBlock - 1) / kZBlock;
     longlong2 m[SRC == kSrcMass64 ? PER : 1];
     float2 a[SRC == kSrcMass64 ? 1 : PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-      const int idx = tid + k * kBlock;
-      if (NE % kBlock == 0 || idx < NE) {
+      const int idx = tid + k * kZBlock;
+      if (NE % kZBlock == 0 || idx < NE) {
         const size_t cell = ((size_t)x * N + y0 + idx / H) * N + 2 * (idx % H);
         if constexpr (SRC == kSrcMass64)
           m[k] = *reinterpret_cast<const longlong2*>((const long long*)in + cell);
@@ -273,8 +281,8 @@ __global__ void __launch_bounds__(kBlock) k_r2c_z(const void* __restrict__ in,
     }
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-      const int idx = tid + k * kBlock;
-      if (NE % kBlock == 0 || idx < NE) {
+      const int idx = tid + k * kZBlock;
+      if (NE % kZBlock == 0 || idx < NE) {
         const int r = idx / H, n = idx % H;
         const size_t cell = ((size_t)x * N + y0 + r) * N + 2 * n;
         float2 d;
@@ -294,10 +302,10 @@ __global__ void __launch_bounds__(kBlock) k_r2c_z(const void* __restrict__ in,
     }
   }
   __syncthreads();
-  fft_rows<H, TZ, kBlock, 2, false>(buf, tws);
+  fft_rows<H, TZ, kZBlock, 2, false>(buf, tws);
   // unpack: X_k = E + w^k O, X_{H-k} = conj(E - w^k O),
   // E = (Z_k + conj Z_{H-k})/2, O = -i (Z_k - conj Z_{H-k})/2
-  for (int idx = tid; idx < TZ * (H / 2 + 1); idx += kBlock) {
+  for (int idx = tid; idx < TZ * (H / 2 + 1); idx += kZBlock) {
     const int r = idx / (H / 2 + 1), k = idx % (H / 2 + 1);
     const float2 zk = buf[r * LP + k];
     const float2 zm = cconj(buf[r * LP + ((H - k) & (H - 1))]);
@@ -309,7 +317,7 @@ __global__ void __launch_bounds__(kBlock) k_r2c_z(const void* __restrict__ in,
     if (k != H / 2) buf[r * LP + H - k] = cconj(csub(e, wo));
   }
   __syncthreads();
-  for (int idx = tid; idx < (H + 1) * TZ; idx += kBlock) {
+  for (int idx = tid; idx < (H + 1) * TZ; idx += kZBlock) {
     const int kz = idx / TZ, r = idx % TZ;
     spec[((size_t)kz * N + x) * N + y0 + r] = buf[r * LP + kz];
   }
@@ -516,7 +524,7 @@ __global__ void __launch_bounds__(RegTiles<1 << LOGN>::XT) k_fft_x_green_reg(flo
 
 // ---------------------------------------------------------------- pass 5
 template <int LOGN>
-__global__ void __launch_bounds__(kBlock) k_c2r_z(const float2* __restrict__ spec,
+__global__ void __launch_bounds__(kZBlock) k_c2r_z(const float2* __restrict__ spec,
                                                   const float2* __restrict__ tw,
                                                   float* __restrict__ out, Batch bt) {
   {
@@ -534,28 +542,28 @@ __global__ void __launch_bounds__(kBlock) k_c2r_z(const float2* __restrict__ spe
   const int zb = (int)xcd_block(blockIdx.x, gridDim.x, Tiles<N>::XG);
   const int x = zb / (N / TZ);
   const int y0 = (zb % (N / TZ)) * TZ;
-  for (int k = tid; k < N; k += kBlock) tws[k] = tw[k];
+  for (int k = tid; k < N; k += kZBlock) tws[k] = tw[k];
   {
     // all of a thread's loads are issued before the first is used
     constexpr int NE = (H + 1) * TZ;
-    constexpr int PER = (NE + kBlock - 1) / kBlock;
+    constexpr int PER = (NE + kZBlock - 1) / kZBlock;
     float2 v[PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-      const int idx = tid + k * kBlock;
-      if (NE % kBlock == 0 || idx < NE)
+      const int idx = tid + k * kZBlock;
+      if (NE % kZBlock == 0 || idx < NE)
         v[k] = spec[((size_t)(idx / TZ) * N + x) * N + y0 + idx % TZ];
     }
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-      const int idx = tid + k * kBlock;
-      if (NE % kBlock == 0 || idx < NE) buf[(idx % TZ) * LP + idx / TZ] = v[k];
+      const int idx = tid + k * kZBlock;
+      if (NE % kZBlock == 0 || idx < NE) buf[(idx % TZ) * LP + idx / TZ] = v[k];
     }
   }
   __syncthreads();
   // pack: E = (X_k + conj X_{H-k})/2, O = (X_k - conj X_{H-k}) conj(w^k)/2,
   // Z_k = E + i O, Z_{H-k} = conj(E) + i conj(O)
-  for (int idx = tid; idx < TZ * (H / 2 + 1); idx += kBlock) {
+  for (int idx = tid; idx < TZ * (H / 2 + 1); idx += kZBlock) {
     const int r = idx / (H / 2 + 1), k = idx % (H / 2 + 1);
     const float2 xk = buf[r * LP + k];
     const float2 xm = cconj(buf[r * LP + H - k]);
@@ -565,8 +573,8 @@ __global__ void __launch_bounds__(kBlock) k_c2r_z(const float2* __restrict__ spe
     if (k != 0 && k != H / 2) buf[r * LP + H - k] = make_float2(e.x + o.y, -e.y + o.x);
   }
   __syncthreads();
-  fft_rows<H, TZ, kBlock, 2, true>(buf, tws);
-  for (int idx = tid; idx < TZ * H; idx += kBlock) {
+  fft_rows<H, TZ, kZBlock, 2, true>(buf, tws);
+  for (int idx = tid; idx < TZ * H; idx += kZBlock) {
     const int r = idx / H, n = idx % H;
     *reinterpret_cast<float2*>(out + ((size_t)x * N + y0 + r) * N + 2 * n) = buf[r * LP + n];
   }
@@ -580,13 +588,13 @@ hipError_t launch_r2c_z(int logn, int src, const void* in, float* delta_out, flo
     constexpr int N_ = 1 << LN;                                                         \
     dim3 g(N_ * (N_ / Tiles<N_>::TZ), bt.count);                                        \
     if (src == kSrcMass64)                                                              \
-      hipLaunchKernelGGL((k_r2c_z<LN, kSrcMass64>), g, dim3(kBlock), 0, s, in, delta_out, \
+      hipLaunchKernelGGL((k_r2c_z<LN, kSrcMass64>), g, dim3(kZBlock), 0, s, in, delta_out, \
                          spec, tw, conv, bt);                                           \
     else if (src == kSrcAcc32)                                                          \
-      hipLaunchKernelGGL((k_r2c_z<LN, kSrcAcc32>), g, dim3(kBlock), 0, s, in, delta_out, \
+      hipLaunchKernelGGL((k_r2c_z<LN, kSrcAcc32>), g, dim3(kZBlock), 0, s, in, delta_out, \
                          spec, tw, conv, bt);                                           \
     else                                                                                \
-      hipLaunchKernelGGL((k_r2c_z<LN, kSrcDelta>), g, dim3(kBlock), 0, s, in, delta_out, \
+      hipLaunchKernelGGL((k_r2c_z<LN, kSrcDelta>), g, dim3(kZBlock), 0, s, in, delta_out, \
                          spec, tw, conv, bt);                                           \
   }
   FDM_LOGN_SWITCH(logn, L_)
@@ -764,7 +772,7 @@ hipError_t launch_c2r_z(int logn, const float2* spec, const float2* tw, float* o
   {                                                                             \
     constexpr int N_ = 1 << LN;                                                 \
     dim3 g(N_ * (N_ / Tiles<N_>::TZ), bt.count);                                \
-    hipLaunchKernelGGL((k_c2r_z<LN>), g, dim3(kBlock), 0, s, spec, tw, out, bt); \
+    hipLaunchKernelGGL((k_c2r_z<LN>), g, dim3(kZBlock), 0, s, spec, tw, out, bt); \
   }
   FDM_LOGN_SWITCH(logn, L_)
 #undef L_
