@@ -69,6 +69,58 @@ def test_suppression_above_the_jeans_scale(result):
     assert np.mean(pc[k > result["k_J_end"]] / p0[k > result["k_J_end"]]) > 2.0
 
 
+def _linear_spline_prediction(res, h_cells, ndir=24):
+    """Linear-theory P_FDM / P_CDM - 1 per shell for the spline coupling.
+
+    A comoving mode k grows as d''+ (2 + dlnE/dlna) d' = [1.5 Om a^-3 G(k) -
+    (hbar/m)^2 k^4 Qf(k) / (4 a^4)] d / E^2 (' = d/dlna, H0 = 1): the
+    linearised Eq. (14) with Q of Eq. (18), whose Jeans balance is Eq. (19).
+    The coupling filters both terms.  Gravity: density on the nodes from the
+    kernel (its transform What), the 7-point Poisson solve (1/K^2),
+    central-difference gradients (D) and CIC interpolation (sinc^2 per axis):
+    G = What prod sinc^2 (k.D) / K^2.  Quantum pressure: the stencil on the
+    kernel density (K^2 for k^2) and the kernel-gradient force (What again):
+    Qf = What^2 K^2 / k^2.  Both runs start on the growing mode; the ratio of
+    the squared growth factors is averaged over directions on each shell."""
+    from scipy.integrate import quad, solve_ivp
+    n, box, hm, om = res["n"], res["box_mpch"], res["hbar_over_m"], res["omega_m"]
+    dx = box / n
+    hk = h_cells * dx
+
+    def what(k):
+        f = lambda r: 4.0 * np.pi * r * r * float(oracle.spline_w(r, hk)) * np.sinc(k * r / np.pi)
+        return quad(f, 0.0, hk, limit=200)[0]
+
+    def growth(k, g, qf):
+        def rhs(x, y):
+            a = np.exp(x)
+            e2 = om / a ** 3 + 1.0 - om
+            dlne = -1.5 * om / a ** 3 / e2
+            src = (1.5 * om / a ** 3 * g - hm ** 2 * k ** 4 * qf / (4.0 * a ** 4)) / e2
+            return [y[1], -(2.0 + dlne) * y[1] + src * y[0]]
+        sol = solve_ivp(rhs, (np.log(res["a_start"]), np.log(res["a_end"])), [1.0, 1.0],
+                        rtol=1e-9, atol=1e-12)
+        return sol.y[0, -1]
+
+    # directions: a Fibonacci sphere
+    i = np.arange(ndir) + 0.5
+    ct = 1.0 - 2.0 * i / ndir
+    ph = np.pi * (1.0 + 5.0 ** 0.5) * i
+    dirs = np.stack([np.sqrt(1 - ct * ct) * np.cos(ph), np.sqrt(1 - ct * ct) * np.sin(ph), ct], 1)
+    out = []
+    for k in res["k"]:
+        w = what(k)
+        r = []
+        for u in dirs:
+            kv = k * u
+            k2 = np.sum(4.0 * np.sin(kv * dx / 2) ** 2) / dx ** 2
+            g = w * np.prod(np.sinc(kv * dx / 2 / np.pi) ** 2) * np.dot(kv, np.sin(kv * dx) / dx) / k2
+            qf = w * w * k2 / k ** 2
+            r.append((growth(k, g, qf) / growth(k, g, 0.0)) ** 2)
+        out.append(np.mean(r) - 1.0)
+    return np.asarray(out)
+
+
 def test_spline_coupling_suppresses_growth(gpu):
     # the same run with the paper's own coupling (pm_spline_step, h = 3.5
     # cells, re-sorted every chunk); the step itself is checked against the
@@ -79,10 +131,20 @@ def test_spline_coupling_suppresses_growth(gpu):
     assert res["finite"] and res["reached_a_end"] and res["coupling"] == "spline"
     k = np.asarray(res["k"])
     rd = np.asarray(res["rel_diff"])
-    assert abs(rd[0]) < 0.02
-    # suppressed just above k_J; towards the grid scale the kernel's own
-    # smoothing (h = 3.5 cells) damps both runs and the difference shrinks
-    above = rd[k > res["k_J_end"]]
-    assert above[0] < -0.2 and above.mean() < -0.05
+    pred = _linear_spline_prediction(res, 3.5)
+    print("k, measured and linear P_FDM/P_CDM - 1:", flush=True)
+    for kk, m_, p_ in zip(k, rd, pred):
+        print(f"  {kk:7.1f} {m_:+.3f} {p_:+.3f}", flush=True)
+    # the largest shell: linear theory predicts no difference
+    assert abs(pred[0]) < 0.005 and abs(rd[0]) < 0.02
+    # above k_J(end) the quantum pressure holds power back, and towards the
+    # grid scale the kernel's smoothing (h = 3.5 cells, What < 0.1 beyond
+    # 100 h/Mpc) takes the difference away in both: at least half of the
+    # linear suppression (the rest is left to mode coupling and to the
+    # particle noise that both runs share) in the first shell above k_J(end)
+    # and on average above it
+    up = k > res["k_J_end"]
+    assert pred[up][0] < -0.2 and rd[up][0] < 0.5 * pred[up][0]
+    assert rd[up].mean() < 0.5 * pred[up].mean()
     pc, p0 = np.asarray(res["P_cdm"]), np.asarray(res["P_start"])
     assert np.mean(pc[k > res["k_J_end"]] / p0[k > res["k_J_end"]]) > 2.0
