@@ -93,7 +93,10 @@ struct pm_ctx {
   hipEvent_t ev_stat = nullptr;
   bool stat_pending = false;
   int stat_age = 0;             // steps since the sort at the sampled step
-  int sort_interval = 10;
+  // adaptive sort interval: it starts at the longest and shortens once the
+  // strays at the end of an interval call for it
+  int sort_interval = 32;
+  int sort_base = 32;           // the interval the stray model gives (before the wide windows)
   bool wide_windows = false;    // aged steps take the wide gather windows
   int since_sort = 1 << 30;     // steps since the last sort
 };
@@ -569,20 +572,27 @@ pm_status pm_force(pm_ctx* c, const float* d_phi, const float* d_q, const void* 
   });
 }
 
-// Adaptive sort interval.  After a fused gather-deposit on a sorted context
-// the stray counters (particles whose deposit fell outside their tile's
-// window) are copied to pinned memory; once the copy has arrived (polled,
-// never waited for) the interval is set from the stray fraction f_k seen k
-// steps after a sort.  The window's halo absorbs small displacements, so
-// strays grow faster than linearly with the age of the sort; modelling
-// them as f_k (j/k)^2 at age j, a sort of cost C every L steps and strays
-// of cost c each cost C/L + c f_k L^2 / (3 k^2) per step, least at
-// L = (kSortBalance k^2 / f_k)^(1/3), with kSortBalance = 3 C / (2 c) in
-// units of strays amounting to all particles, tuned on evolved 256^3 boxes
-// (best L = 2 at a = 0.5; no strays at all at a = 0.01).
+// Adaptive sort interval.  After the last fused gather-deposit of an
+// interval the stray counters (particles whose deposit fell outside their
+// tile's window) are copied to pinned memory; once the copy has arrived
+// (polled, never waited for) the interval is set from the stray fraction
+// f_k seen k steps after the sort.  The window's halo absorbs small
+// displacements, so strays grow faster than linearly with the age of the
+// sort; modelling them as f_k (j/k)^2 at age j, a sort of cost C every L
+// steps and strays of cost c each cost C/L + c f_k L^2 / (3 k^2) per step,
+// least at L = (kSortBalance k^2 / f_k)^(1/3), with kSortBalance = 3 C / (2 c)
+// in units of strays amounting to all particles.  On the 256^3 box at
+// a = 0.5 the interval settles at 6-7 steps (plus one step on the wide
+// windows): 0.72-0.73 ms per step, against 0.74-0.76 for any fixed interval
+// of 4 to 8 steps and 0.96 when the counters were sampled right after each
+// sort (where the halo still hides the motion).  From the Zel'dovich state
+// at a = 0.01 no strays appear and the interval stays at its maximum.
 namespace {
 
-constexpr double kSortBalance = 0.02;
+#ifndef FDM_SORT_BALANCE
+#define FDM_SORT_BALANCE 0.02
+#endif
+constexpr double kSortBalance = FDM_SORT_BALANCE;
 constexpr int kSortIntervalMax = 32;
 #ifndef FDM_WIDE_INTERVAL
 #define FDM_WIDE_INTERVAL 8
@@ -619,17 +629,23 @@ void poll_sort_stat(pm_ctx* c) {
   for (int k = 0; k < kStraySlices; ++k) strays += c->h_stat[k * kStrayStride];
   const double f = strays / (double)c->np;
   const double k = c->stat_age > 0 ? c->stat_age : 1;
-  int interval = kSortIntervalMax;
+  // Samples are taken at the end of an interval (strays stay near zero while
+  // the halo absorbs the motion and then rise faster than the model, so
+  // early samples would overestimate the interval).  A whole interval
+  // without strays doubles it.
+  int base = c->sort_base;
   if (f > 0.0) {
     const double l = cbrt(kSortBalance * k * k / f);
-    interval = l < 1.0 ? 1 : (l > kSortIntervalMax ? kSortIntervalMax : (int)l);
+    base = l < 1.0 ? 1 : (l > kSortIntervalMax ? kSortIntervalMax : (int)l);
+  } else if (k >= base) {
+    base = std::min(2 * base, kSortIntervalMax);
   }
+  c->sort_base = base;
   // Strays are counted against the narrow windows.  Where they set a short
   // interval, the steps after the first since a sort take the wide windows,
   // which absorb about one more step of motion: one step more between sorts.
-  c->wide_windows = interval <= kWideInterval;
-  if (c->wide_windows) interval = std::min(interval + kWideExtra, kSortIntervalMax);
-  c->sort_interval = interval;
+  c->wide_windows = base <= kWideInterval;
+  c->sort_interval = c->wide_windows ? std::min(base + kWideExtra, kSortIntervalMax) : base;
 }
 
 }  // namespace
@@ -781,7 +797,9 @@ static pm_status step_impl(pm_ctx* c, void* d_pos, float* d_vel, const double* t
     }));
     ++c->since_sort;
     if (en && (s > 0 || row0)) PM_TRY(energy_row(s));
-    if (sort_auto && !c->stat_pending) PM_TRY(sample_sort_stat(c));
+    // the last step before the next sort samples the strays of the interval
+    if (sort_auto && !c->stat_pending && c->since_sort >= c->sort_interval)
+      PM_TRY(sample_sort_stat(c));
     close = kick(c->p, tm, t1);
     if (s + 1 < nsteps && !en) {
       const Kick kn = merged(s + 1, close);
