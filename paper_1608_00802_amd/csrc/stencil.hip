@@ -166,7 +166,7 @@ __device__ __forceinline__ float s_of(float d, const QConst& qc) {
 }
 
 template <int LOGN, bool FIXED, int OUT>
-__global__ void __launch_bounds__(kQBlock) k_qpot_tiled(const float* __restrict__ delta,
+__global__ void __launch_bounds__(kQBlock, OUT == kOutEnergy ? 1 : 8) k_qpot_tiled(const float* __restrict__ delta,
                                                        const long long* __restrict__ mass,
                                                        const float* __restrict__ phi,
                                                        float* __restrict__ q, QConst qc,
@@ -250,11 +250,20 @@ __global__ void __launch_bounds__(kQBlock) k_qpot_tiled(const float* __restrict_
     for (int w = 0; w < kQBlock / 64; ++w) f |= nflag[slot][w];
     return f != 0;
   };
-  auto sd = [&](size_t j) {
-    double r = (double)mass[j] * qc.inv_mbar;
+  auto sdv = [&](long long m) {
+    double r = (double)m * qc.inv_mbar;
     r = r > qc.floor_d ? r : qc.floor_d;
     return sqrt_d(r);
   };
+  auto sd = [&](size_t j) { return sdv(mass[j]); };
+  // The integer mass of the next plane, loaded while this one is computed
+  // once the next plane is known to hold a near-empty cell (block-uniform),
+  // so its FP64 values do not wait for a full load latency (evolved 256^3
+  // box: 119 -> 95 us; it takes the last 2 of the 64 VGPRs that two blocks
+  // per CU allow, hence the launch bound of 8 waves per SIMD; the energy
+  // form keeps its 80 VGPRs and one block per CU rather than spill).
+  long long mpre[PER];
+  bool mpre_ok = false;
   const int cc = (ty + 1) * PZ + tz + 1;
   auto inplane = [&](const float* buf) {
     return (buf[cc - PZ] + buf[cc + PZ]) + (buf[cc - 1] + buf[cc + 1]);
@@ -296,10 +305,26 @@ __global__ void __launch_bounds__(kQBlock) k_qpot_tiled(const float* __restrict_
     double d_c = 0.0, d_ym = 0.0, d_yp = 0.0, d_zm = 0.0, d_zp = 0.0;
     if constexpr (FIXED) {
       if (near_cur || near_next) {
+        if (!mpre_ok) {
+#pragma unroll
+          for (int k = 0; k < PER; ++k) {
+            const int c = threadIdx.x + k * kQBlock;
+            if (c < PY * PZ) mpre[k] = mass[plane_index(x, c)];
+          }
+        }
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
           const int c = threadIdx.x + k * kQBlock;
-          if (c < PY * PZ) dpl[c] = sd(plane_index(x, c));
+          if (c < PY * PZ) dpl[c] = sdv(mpre[k]);
+        }
+        // plane x + 1 holds a near-empty cell: its FP64 values will be built
+        mpre_ok = near_next && x + 1 < x0 + QX;
+        if (mpre_ok) {
+#pragma unroll
+          for (int k = 0; k < PER; ++k) {
+            const int c = threadIdx.x + k * kQBlock;
+            if (c < PY * PZ) mpre[k] = mass[plane_index(x + 1, c)];
+          }
         }
         __syncthreads();
         d_c = dpl[cc];
