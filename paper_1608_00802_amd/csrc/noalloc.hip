@@ -59,10 +59,10 @@ __global__ void k_static_tables(float2* __restrict__ tw, float* __restrict__ s2,
 extern "C" pm_status pm_poisson_static(int32_t n_mesh, double S, const float* d_delta,
                                        float* d_phi, void* hip_stream) {
   if (!d_delta || !d_phi || !isfinite(S)) return PM_EINVAL;
+  if (n_mesh < 16 || (n_mesh & (n_mesh - 1)) != 0) return PM_EUNSUPPORTED;
+  if (n_mesh > kStaticMaxN) return PM_ENOMEM;
   int logn = 0;
   while ((1 << logn) < n_mesh) ++logn;
-  if ((1 << logn) != n_mesh || logn < 4) return PM_EUNSUPPORTED;
-  if (n_mesh > kStaticMaxN) return PM_ENOMEM;
   void* base = nullptr;
   const pm_status st = scratch_ptr(&base);
   if (st != PM_OK) return st;
