@@ -130,9 +130,10 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 int ilog2_exact(int n) {
+  if (n <= 0 || (n & (n - 1)) != 0) return -1;
   int l = 0;
   while ((1 << l) < n) ++l;
-  return (1 << l) == n ? l : -1;
+  return l;
 }
 
 struct Layout {

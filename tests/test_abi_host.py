@@ -78,6 +78,10 @@ def test_workspace_bytes(lib):
     (dict(n_mesh=48), _lib.PM_EUNSUPPORTED),
     (dict(n_mesh=8), _lib.PM_EUNSUPPORTED),
     (dict(n_mesh=1024), _lib.PM_EUNSUPPORTED),
+    (dict(n_mesh=0), _lib.PM_EUNSUPPORTED),
+    (dict(n_mesh=-64), _lib.PM_EUNSUPPORTED),
+    (dict(n_mesh=2 ** 30 + 1), _lib.PM_EUNSUPPORTED),
+    (dict(n_mesh=2 ** 31 - 1), _lib.PM_EUNSUPPORTED),
     (dict(n_part=0), _lib.PM_EINVAL),
     (dict(box=0.0), _lib.PM_EINVAL),
     (dict(box=float("nan")), _lib.PM_EINVAL),
@@ -108,6 +112,18 @@ def test_init_rejects_before_device_access(lib):
     assert lib.pm_init(ctypes.byref(p), ctypes.c_void_p(0x100000), need - 256, None,
                        ctypes.byref(ctx)) == _lib.PM_ENOMEM
     assert ctx.value is None
+
+
+def test_poisson_static_rejects_before_device_access(lib):
+    # argument errors come back before the call touches a device (none here)
+    fake = ctypes.c_void_p(0x100000)
+    for n in (0, 8, 48, 100, 2 ** 31 - 1):
+        assert lib.pm_poisson_static(n, 1.0, fake, fake, None) == _lib.PM_EUNSUPPORTED, n
+    for n in (256, 512, 2 ** 30):
+        assert lib.pm_poisson_static(n, 1.0, fake, fake, None) == _lib.PM_ENOMEM, n
+    assert lib.pm_poisson_static(64, 1.0, None, fake, None) == _lib.PM_EINVAL
+    assert lib.pm_poisson_static(64, 1.0, fake, None, None) == _lib.PM_EINVAL
+    assert lib.pm_poisson_static(64, float("nan"), fake, fake, None) == _lib.PM_EINVAL
 
 
 def test_null_context_calls(lib):
