@@ -117,10 +117,12 @@ typedef struct pm_ctx pm_ctx;
 #define PM_SORT_EVERY(k) ((((int32_t)(k)) & 0xffff) << 8)
 /* Sort by tile at an interval the context adapts to how fast particles
  * leave their tiles (fixed-point form only; PM_EUNSUPPORTED otherwise).
- * The context samples the count of particles whose deposit left their
- * tile's window into pinned host memory (allocated on first use, freed by
- * pm_destroy) and reads it once it has arrived, without waiting: the
- * interval, and so the particle order, may depend on timing, never the
+ * At the end of each interval the context samples the count of particles
+ * whose deposit left their tile's window into pinned host memory (allocated
+ * on first use, freed by pm_destroy) and reads it once it has arrived,
+ * without waiting; the interval starts at 32 steps, shortens where that
+ * count calls for it and doubles after an interval without such particles.
+ * The interval, and so the particle order, may depend on timing, never the
  * state as a set of particles.  Where that count is high (clustered
  * states), steps after the first since a sort use larger tile windows and
  * the interval is one step longer; results do not depend on the windows.
