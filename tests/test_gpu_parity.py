@@ -420,11 +420,13 @@ def test_tiled_deposit_equals_direct(pm, gpu, precision):
         assert rel_l2(d_t.cpu().numpy(), d_d.cpu().numpy()) < 1e-6
 
 
-def test_sorted_steps_vs_oracle(pm, gpu):
-    """Twenty steps with a sort every 5 steps (tiled deposit and gather)
-    against the oracle, matched through the permuted ids."""
+@pytest.mark.parametrize("n", [16, 32, 64])
+def test_sorted_steps_vs_oracle(pm, gpu, n):
+    """Twenty steps with a sort before each half (tiled deposit and gather)
+    against the oracle, matched through the permuted ids; at 16^3 and 32^3
+    the 8 x 8 x 32 tile is clamped to the mesh along z (one tile row, and at
+    16^3 tile windows that wrap onto themselves)."""
     import torch
-    n = 64
     box = 10.0 * n / 256
     st = zeldovich_state(n, box, 0.01, seed=1, m_ev=1e-22)
     lp, op = cosmo_setup(n, box, 1e-22)
