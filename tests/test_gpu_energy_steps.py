@@ -90,6 +90,25 @@ def test_step_energies_comoving_vs_oracle(pm, gpu, sort):
     _compare(r2[1:], ref2[1:], 1e-5, "continued call")
 
 
+@pytest.mark.timeout(600)
+def test_step_energies_256_bench_state(pm, gpu):
+    """The energies of the timed 256^3 step (comoving 10 Mpc/h, Zel'dovich
+    start at a = 0.01, adaptive sort, two steps) against the oracle's along
+    its own trajectory."""
+    import torch
+    n = 256
+    st = zeldovich_state(n, 10.0, 0.01, seed=1, m_ev=1e-22)
+    lp, op = cosmo_setup(n, 10.0, 1e-22)
+    ctx = pm.PMContext(lp, device=gpu)
+    pos, vel = to_device(st, gpu)
+    times = list(0.01 * np.exp(np.arange(3) * math.log(100.0) / 500))
+    en = torch.full((len(times), 4), float("nan"), dtype=torch.float64, device=gpu)
+    ctx.step_energies(pos, vel, times, en, flags=pm.PM_SORT_AUTO)
+    torch.cuda.synchronize()
+    ref, _, _ = _oracle_series(st.pos, st.vel, op, times)
+    _compare(en.cpu().numpy(), ref, 1e-5, "comoving 256^3, adaptive sort")
+
+
 @pytest.mark.parametrize("precision", [1, 0])
 def test_step_energies_static_single_mode(pm, gpu, precision):
     """Static box of the single-mode problem: the rows follow the oracle's
