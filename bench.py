@@ -63,7 +63,9 @@ def alg_bytes(n: int, npart: int, steps: int = 20) -> dict:
         # fused deposit of the drifted particles (read+write of the int64
         # mass mesh once)
         "gather_kick_drift": 48 * npart + (4 * (k - 1) + 8) * cells // k + 16 * cells,
-        "kick": 36 * npart + 8 * cells,
+        # closing half-kick of a call: phi and Q in; on a sorted context it
+        # also copies the positions from the workspace copies back
+        "kick": 48 * npart + 8 * cells,
         "sort_count": 12 * npart + 8 * npart,        # positions in, key and rank out
         "sort_scatter": 8 * npart + 48 * npart,      # key, rank, pos+vel in, copies out
         "sort_copy": 48 * npart,
