@@ -151,7 +151,17 @@ __global__ void __launch_bounds__(kBlock) k_qpot(const float* __restrict__ delta
 #ifndef FDM_QPOT_QY
 #define FDM_QPOT_QY 32   // 256^3: 51.1 us against 52.2 (16 rows) and 55.4 (8 rows)
 #endif
-constexpr int QY = FDM_QPOT_QY, QZ = 32, QX = FDM_QPOT_QX;
+constexpr int QY = FDM_QPOT_QY, QZ = 32;
+#ifndef FDM_QPOT_QX_SMALL
+#define FDM_QPOT_QX_SMALL 4
+#endif
+// x-planes per block: fewer on meshes up to 128^3, so that a run (or a
+// batch slot) still spreads over enough blocks to fill the CUs (128^3:
+// 512 blocks of 4 planes instead of 128 of 16; the extra x-halo planes are
+// cache hits at these sizes)
+__host__ __device__ constexpr int qpot_qx(int logn) {
+  return logn <= 7 ? FDM_QPOT_QX_SMALL : FDM_QPOT_QX;
+}
 constexpr int kQBlock = QY * QZ;   // threads per block of the tiled stencil
 #ifndef FDM_XCD_QPOT
 #define FDM_XCD_QPOT 8   // a z-row of blocks per XCD at a time (256^3: 64 -> 62 us)
@@ -203,6 +213,7 @@ __global__ void __launch_bounds__(kQBlock, OUT == kOutEnergy ? 1 : 8) k_qpot_til
   const int nby = N / QY, nbz = N / QZ;
   const int b = (int)xcd_block(blockIdx.x, gridDim.x, FDM_XCD_QPOT);
   const int bz = b % nbz, by = (b / nbz) % nby, bx = b / (nbz * nby);
+  constexpr int QX = qpot_qx(LOGN);
   const int y0 = by * QY, z0 = bz * QZ, x0 = bx * QX;
   const int ty = threadIdx.x / QZ, tz = threadIdx.x % QZ;
   const int y = y0 + ty, z = z0 + tz;
@@ -390,7 +401,7 @@ __global__ void __launch_bounds__(kQBlock, OUT == kOutEnergy ? 1 : 8) k_qpot_til
 
 int qpot_blocks(int logn) {
 #ifndef FDM_QPOT_SIMPLE
-  if (logn >= 5) return (int)(((size_t)1 << (3 * logn)) / ((size_t)QY * QZ * QX));
+  if (logn >= 5) return (int)(((size_t)1 << (3 * logn)) / ((size_t)QY * QZ * qpot_qx(logn)));
 #endif
   return (int)(((size_t)1 << (3 * logn)) / kBlock);
 }
