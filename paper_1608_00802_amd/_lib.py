@@ -87,6 +87,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built: call __graft_entry__.build() or "
                           "python -m paper_1608_00802_amd.build")
+    # torch first: the library must bind to the HIP runtime that owns torch's
+    # streams and allocations (torch ships its own); loaded before torch, it
+    # would bring up a second runtime and every call on torch's memory fails
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     P = POINTER
     sig = {
