@@ -175,6 +175,9 @@ constexpr int kRegBlock = 128;   // threads per block of the register-FFT y pass
 #ifndef FDM_FFTX_ORDER
 #define FDM_FFTX_ORDER 0   // lanes across the block's columns (see x_item)
 #endif
+#ifndef FDM_FFTX_BIG
+#define FDM_FFTX_BIG 64    // meshes from this size on take the 256-thread, 16-column x pass
+#endif
 #ifndef FDM_FFTX_PAD
 #define FDM_FFTX_PAD -1    // extra float2 between the x pass's LDS columns (-1: per N)
 #endif
@@ -336,18 +339,19 @@ struct RegTiles {
   static constexpr int RMAX = R1 > R2 ? R1 : R2;
   static constexpr int RY0 = kRegBlock / R2;                       // y-pass rows per block
   static constexpr int RY = RY0 < N ? RY0 : N;
-  // x pass: 256 threads and 16 columns from N = 256 on (whole 128-byte lines
+  // x pass: 256 threads and 16 columns from N = 64 on (whole 128-byte lines
   // per row; 256^3: 29.6 us against 37.5 with 64 threads and 4 columns and
-  // 31.8 with 128 and 8; 512^3: 266 against 385 us with 128 and 8), 64 and 4
-  // below; blocks that share a line of a column run are grouped on one XCD
-  static constexpr int XT = FDM_FFTX_XT ? FDM_FFTX_XT : (N < 256 ? 64 : 256);  // threads
+  // 31.8 with 128 and 8; 512^3: 266 against 385 us with 128 and 8; 128^3:
+  // 12.2 against 13.5 us with 64 and 4), 64 threads below; blocks that share
+  // a line of a column run are grouped on one XCD
+  static constexpr int XT = FDM_FFTX_XT ? FDM_FFTX_XT : (N < FDM_FFTX_BIG ? 64 : 256);  // threads
   static constexpr int TC0 =
-      FDM_FFTX_TC ? FDM_FFTX_TC : (N < 256 ? ((XT / RMAX > 4) ? XT / RMAX : 4) : 16);
+      FDM_FFTX_TC ? FDM_FFTX_TC : (N < FDM_FFTX_BIG ? ((XT / RMAX > 4) ? XT / RMAX : 4) : 16);
   static constexpr int TC = TC0 < N ? TC0 : N;                     // x-pass columns per block
   static constexpr int XG = TC < 16 ? 16 / TC : 1;                 // XCD group
   // padding between the columns of the LDS exchange (2 entries with 16
   // columns: their 128-byte runs otherwise start in the same banks)
-  static constexpr int PAD = FDM_FFTX_PAD >= 0 ? FDM_FFTX_PAD : (N >= 256 ? 2 : 0);
+  static constexpr int PAD = FDM_FFTX_PAD >= 0 ? FDM_FFTX_PAD : (N >= FDM_FFTX_BIG ? 2 : 0);
 };
 
 // Work item `it` of the x pass: column c of the block's TC columns and index
