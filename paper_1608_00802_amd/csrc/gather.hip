@@ -106,6 +106,16 @@ __device__ __forceinline__ void interp_grad(const float f[3], At&& at, float g[3
   g[2] = -0.5f * gz;
 }
 
+// Low 32 bits of rint(a * b), ties to even: the drift in fixed-point units,
+// wrapped.  For |a * b| < 2^51 (a drift below 2^19 box lengths), adding
+// 1.5 * 2^52 rounds the product to an integer and leaves it, two's
+// complement, in the low mantissa bits.  No fma contraction.
+__device__ __forceinline__ uint32_t rint_mul_low32(double a, double b) {
+#pragma clang fp contract(off)
+  const double t = a * b;
+  return (uint32_t)__double_as_longlong(t + 0x1.8p52);
+}
+
 // Apply the result for particle p: store the force, or kick (and drift).
 template <int LOGN, bool FIXED, int MODE>
 __device__ __forceinline__ void push(void* __restrict__ pos, float* __restrict__ vel,
@@ -130,8 +140,7 @@ __device__ __forceinline__ void push(void* __restrict__ pos, float* __restrict__
       vel[d * np + p] = v;
       if constexpr (MODE == kKickDrift) {
         if constexpr (FIXED) {
-          const long long inc = __double2ll_rn((double)v * fd_units);
-          unew[d] = u[d] + (uint32_t)(unsigned long long)inc;
+          unew[d] = u[d] + rint_mul_low32((double)v, fd_units);
           static_cast<uint32_t*>(pos)[d * np + p] = unew[d];
         } else {
           float x = xf[d] + v * (float)fd_units;
@@ -145,12 +154,37 @@ __device__ __forceinline__ void push(void* __restrict__ pos, float* __restrict__
   }
 }
 
+// The potential the gather differentiates at one node.  With Q it is
+// F = fg phi + fq Q, with the stencil's psi rounding (fq Q added by one
+// fma); without Q it is phi (or psi) itself, and fg multiplies the
+// interpolated gradient instead (gradient and interpolation are linear; for
+// psi, fg = 1).
 template <int LOGN, bool HAS_Q>
 __device__ __forceinline__ float mesh_f(const float* __restrict__ phi, const float* __restrict__ q,
                                         const GatherConst& gc, size_t idx) {
-  // the same rounding as the stencil's psi output: fq * Q added by one fma
   if constexpr (HAS_Q) return fmaf(gc.fq, q[idx], gc.fg * phi[idx]);
-  return gc.fg * phi[idx];
+  return phi[idx];
+}
+
+// The factor on the interpolated gradient (fg without Q, see mesh_f).
+template <bool HAS_Q>
+__device__ __forceinline__ void scale_grad(const GatherConst& gc, float g[3]) {
+  if constexpr (!HAS_Q) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) g[d] *= gc.fg;
+  }
+}
+
+// mesh_f at a byte offset below 2^32 (the mesh is at most 512^3 floats).
+template <bool HAS_Q>
+__device__ __forceinline__ float mesh_f_at(const float* __restrict__ phi,
+                                           const float* __restrict__ q, const GatherConst& gc,
+                                           uint32_t off) {
+  const float p = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(phi) + off);
+  if constexpr (HAS_Q)
+    return fmaf(gc.fq, *reinterpret_cast<const float*>(reinterpret_cast<const char*>(q) + off),
+                gc.fg * p);
+  return p;
 }
 
 // Weights of the drifted particle for the fused deposit.
@@ -241,6 +275,7 @@ __global__ void __launch_bounds__(kBlock) k_gather(void* __restrict__ pos,
       interp_grad(f, [&](int a, int b, int c) {
         return mesh_f<LOGN, HAS_Q>(phi, q, gc, node(a, b, c));
       }, g);
+      scale_grad<HAS_Q>(gc, g);
 #pragma unroll
       for (int d = 0; d < 3; ++d) vk[d] = vin[d];
     }
@@ -267,8 +302,14 @@ __global__ void __launch_bounds__(kBlock) k_gather(void* __restrict__ pos,
 // particles that left it read the mesh directly.
 // WIDE: a one-cell larger gather window and a two-cell deposit halo, for
 // steps whose particles have moved since the sort in a clustered state.
+// Waves per SIMD that the LDS windows leave room for (three 512-thread
+// blocks per CU with the narrow windows, two with the wide ones or two
+// energy-form windows); the register budget is held to that.
+constexpr int gather_waves(int wide, bool two_windows) { return wide || two_windows ? 4 : 6; }
+
 template <int LOGN, bool FIXED, bool HAS_Q, int MODE, bool DEP, int WIDE = 0, bool EN = false>
-__global__ void __launch_bounds__(kGatherBlock) k_gather_tiled(void* __restrict__ pos,
+__global__ void __launch_bounds__(kGatherBlock, gather_waves(WIDE, EN && HAS_Q))
+    k_gather_tiled(void* __restrict__ pos,
                                                          float* __restrict__ vel,
                                                          const float* __restrict__ phi,
                                                          const float* __restrict__ q, int64_t np,
@@ -361,7 +402,7 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather_tiled(void* __restrict_
 #pragma unroll
     for (int k = 0; k < WPER; ++k) {
       const int c = threadIdx.x + k * kGatherBlock;
-      if (WN % kGatherBlock == 0 || c < WN) win[c] = gc.fg * wphi[k];   // the rounding of mesh_f
+      if (WN % kGatherBlock == 0 || c < WN) win[c] = wphi[k];   // mesh_f without Q
     }
   }
   if constexpr (DEP)
@@ -390,7 +431,9 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather_tiled(void* __restrict_
     const int rx = (ic[0] - ox + HG) & MASK, ry = (ic[1] - oy + HG) & MASK,
               rz = (ic[2] - oz + HG) & MASK;
     const bool in_win = rx < TX + 2 * HG && ry < TY + 2 * HG && rz < TZ + 2 * HG;
-    auto lds = [&](int a, int b, int c) { return ((rx + a) * WY + ry + b) * WZ + rz + c; };
+    // one base index; the 32 nodes at constant offsets from it
+    const int lbase = (rx * WY + ry) * WZ + rz;
+    auto lds = [&](int a, int b, int c) { return lbase + (a * WY + b) * WZ + c; };
     auto node = [&](int a, int b, int c) {
       return ((size_t)((ic[0] + a - 1) & MASK) * N + ((ic[1] + b - 1) & MASK)) * N +
              ((ic[2] + c - 1) & MASK);
@@ -412,10 +455,20 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather_tiled(void* __restrict_
       if (in_win) {
         interp_grad(f, [&](int a, int b, int c) { return win[lds(a, b, c)]; }, g);
       } else {
+        // byte offsets of the 4 x 4 x 4 neighbourhood from per-axis terms
+        // (disjoint bit fields: one or per node)
+        uint32_t bo_x[4], bo_y[4], bo_z[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          bo_x[a] = (uint32_t)((ic[0] + a - 1) & MASK) << (2 * LOGN + 2);
+          bo_y[a] = (uint32_t)((ic[1] + a - 1) & MASK) << (LOGN + 2);
+          bo_z[a] = (uint32_t)((ic[2] + a - 1) & MASK) << 2;
+        }
         interp_grad(f, [&](int a, int b, int c) {
-          return mesh_f<LOGN, HAS_Q>(phi, q, gc, node(a, b, c));
+          return mesh_f_at<HAS_Q>(phi, q, gc, bo_x[a] | bo_y[b] | bo_z[c]);
         }, g);
       }
+      scale_grad<HAS_Q>(gc, g);
 #pragma unroll
       for (int d = 0; d < 3; ++d) vk[d] = vin[d];
     }
@@ -423,17 +476,33 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather_tiled(void* __restrict_
     float xnew[3];
     push<LOGN, FIXED, MODE>(pos, vel, acc, np, p, g, vk, u, xf, gc.fd_units, unew, xnew, mass_v);
     if constexpr (DEP) {
-      int jx, jy, jz;
+      // natural corner order (consecutive lanes of a wave add to neighbouring
+      // cells together); the fixed-point remainder d goes to the heaviest
+      // corner in a ninth add where it is not zero
+      int jx, jy, jz, big = 0, dfix = 0;
       T w[8];
-      new_weights<LOGN, FIXED>(unew, xnew, jx, jy, jz, w);
+      if constexpr (FIXED)
+        fixed_weights_split<LOGN>(unew[0], unew[1], unew[2], jx, jy, jz, w, big, dfix);
+      else
+        float_weights<LOGN>(xnew[0], xnew[1], xnew[2], jx, jy, jz, w);
       const int sx = (jx - ox + HD) & MASK, sy = (jy - oy + HD) & MASK,
                 sz = (jz - oz + HD) & MASK;
       const bool inside = sx < TX + 2 * HD && sy < TY + 2 * HD && sz < TZ + 2 * HD;
       if (inside) {
+        const int a0 = (sx * DY + sy) * DZ + sz;
 #pragma unroll
         for (int c = 0; c < 8; ++c)
-          atomicAdd(&dacc[((sx + (c >> 2)) * DY + sy + ((c >> 1) & 1)) * DZ + sz + (c & 1)], w[c]);
+          atomicAdd(&dacc[a0 + ((c >> 2) * DY + ((c >> 1) & 1)) * DZ + (c & 1)], w[c]);
+        if constexpr (FIXED)
+          if (dfix != 0)
+            atomicAdd(&dacc[a0 + ((big >> 2) * DY + ((big >> 1) & 1)) * DZ + (big & 1)],
+                      (T)(long long)dfix);
       } else {
+        if constexpr (FIXED) {
+#pragma unroll
+          for (int c = 0; c < 8; ++c)
+            if (c == big) w[c] += (T)(long long)dfix;
+        }
         deposit_global<LOGN>(static_cast<T*>(mass_v), jx, jy, jz, w);
       }
       // count strays (always against the narrow deposit window, so that the
