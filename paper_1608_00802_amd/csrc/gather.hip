@@ -50,14 +50,30 @@ __device__ __forceinline__ void decode_cell(const uint32_t raw[3], int ic[3], fl
   }
 }
 
+// Component d of particle p in a structure-of-arrays buffer of 4-byte
+// words.  With a 32-bit index (p < 2^30, which the particle limit of 8 N^3
+// <= 2^30 keeps) the address is a per-component base, uniform over the
+// block, plus a 32-bit byte offset.
+template <typename T>
+__device__ __forceinline__ T& soa(T* base, int64_t np, int d, int64_t p) {
+  return base[d * np + p];
+}
+template <typename T>
+__device__ __forceinline__ T& soa(T* base, int64_t np, int d, unsigned p) {
+  static_assert(sizeof(T) == 4, "4-byte words");
+  using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+  return *reinterpret_cast<T*>(reinterpret_cast<B*>(base + d * np) + (p << 2));
+}
+
 // The position words and velocity of particle p.
+template <typename P>
 __device__ __forceinline__ void load_particle(const void* __restrict__ pos,
-                                              const float* __restrict__ vel, int64_t np,
-                                              int64_t p, uint32_t raw[3], float v[3]) {
+                                              const float* __restrict__ vel, int64_t np, P p,
+                                              uint32_t raw[3], float v[3]) {
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    raw[d] = static_cast<const uint32_t*>(pos)[d * np + p];
-    v[d] = vel ? vel[d * np + p] : 0.0f;
+    raw[d] = soa(static_cast<const uint32_t*>(pos), np, d, p);
+    v[d] = vel ? soa(vel, np, d, p) : 0.0f;
   }
 }
 
@@ -117,37 +133,37 @@ __device__ __forceinline__ uint32_t rint_mul_low32(double a, double b) {
 }
 
 // Apply the result for particle p: store the force, or kick (and drift).
-template <int LOGN, bool FIXED, int MODE>
+template <int LOGN, bool FIXED, int MODE, typename P>
 __device__ __forceinline__ void push(void* __restrict__ pos, float* __restrict__ vel,
-                                     float* __restrict__ acc, int64_t np, int64_t p,
+                                     float* __restrict__ acc, int64_t np, P p,
                                      const float g[3], const float vin[3], const uint32_t u[3],
                                      const float xf[3], double fd_units, uint32_t unew[3],
                                      float xnew[3], void* __restrict__ pos_out = nullptr) {
   constexpr int N = 1 << LOGN;
   if constexpr (MODE == kForce) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) acc[d * np + p] = g[d];
+    for (int d = 0; d < 3; ++d) soa(acc, np, d, p) = g[d];
   } else if constexpr (MODE == kKickCopy) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      acc[d * np + p] = vin[d] + g[d];
-      static_cast<uint32_t*>(pos_out)[d * np + p] = FIXED ? u[d] : __float_as_uint(xf[d]);
+      soa(acc, np, d, p) = vin[d] + g[d];
+      soa(static_cast<uint32_t*>(pos_out), np, d, p) = FIXED ? u[d] : __float_as_uint(xf[d]);
     }
   } else {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const float v = vin[d] + g[d];
-      vel[d * np + p] = v;
+      soa(vel, np, d, p) = v;
       if constexpr (MODE == kKickDrift) {
         if constexpr (FIXED) {
           unew[d] = u[d] + rint_mul_low32((double)v, fd_units);
-          static_cast<uint32_t*>(pos)[d * np + p] = unew[d];
+          soa(static_cast<uint32_t*>(pos), np, d, p) = unew[d];
         } else {
           float x = xf[d] + v * (float)fd_units;
           x = x - (float)N * floorf(x * (1.0f / (float)N));
           if (x >= (float)N) x = 0.0f;
           xnew[d] = x;
-          static_cast<float*>(pos)[d * np + p] = x;
+          soa(static_cast<float*>(pos), np, d, p) = x;
         }
       }
     }
@@ -409,6 +425,7 @@ __global__ void __launch_bounds__(kGatherBlock, gather_waves(WIDE, EN && HAS_Q))
     for (int c = threadIdx.x; c < DX * DY * DZ; c += kGatherBlock) dacc[c] = (T)0;
   __syncthreads();
   double ksum = 0.0;
+  unsigned my_stray = 0;   // this thread's deposits outside the narrow window
   for (unsigned p = lo + threadIdx.x; p < hi; p += kGatherBlock) {
     int ic[3];
     float f[3], xf[3], vin[3];
@@ -506,16 +523,18 @@ __global__ void __launch_bounds__(kGatherBlock, gather_waves(WIDE, EN && HAS_Q))
         deposit_global<LOGN>(static_cast<T*>(mass_v), jx, jy, jz, w);
       }
       // count strays (always against the narrow deposit window, so that the
-      // sort interval chosen from them does not depend on the window used):
-      // one LDS atomic per wave
+      // sort interval chosen from them does not depend on the window used)
       constexpr int HN = kDepHalo;
       const bool inside_n = ((jx - ox + HN) & MASK) < TX + 2 * HN &&
                             ((jy - oy + HN) & MASK) < TY + 2 * HN &&
                             ((jz - oz + HN) & MASK) < TZ + 2 * HN;
-      const unsigned long long m = __ballot(!inside_n);
-      if (m && (threadIdx.x & 63) == __ffsll((long long)__ballot(1)) - 1)
-        atomicAdd(&n_stray, (unsigned)__popcll(m));
+      my_stray += inside_n ? 0u : 1u;
     }
+  }
+  if constexpr (DEP) {
+    // one LDS add per wave
+    for (int off = 32; off > 0; off >>= 1) my_stray += __shfl_down(my_stray, off, 64);
+    if ((threadIdx.x & 63) == 0 && my_stray) atomicAdd(&n_stray, my_stray);
   }
   if constexpr (EN) {
     __shared__ double kred[kGatherBlock / 64];
