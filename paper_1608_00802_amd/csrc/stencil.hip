@@ -166,7 +166,7 @@ constexpr int kQBlock = QY * QZ;   // threads per block of the tiled stencil
 #ifndef FDM_XCD_QPOT
 #define FDM_XCD_QPOT 8   // a z-row of blocks per XCD at a time (256^3: 64 -> 62 us)
 #endif
-static_assert(kQBlock % 64 == 0, "whole waves");
+static_assert(kQBlock % 64 == 0 && kQBlock / 64 <= 64, "whole waves, one flag per lane");
 
 template <bool FIXED>
 __device__ __forceinline__ float s_of(float d, const QConst& qc) {
@@ -254,12 +254,12 @@ __global__ void __launch_bounds__(kQBlock, OUT == kOutEnergy ? 1 : 8) k_qpot_til
     }
   };
   // after the barrier that follows commit(.., slot)
+  // (lane w reads wave w's flag; one vote over the wave)
   auto plane_near = [&](int slot) {
     if (!use64) return false;
-    uint32_t f = 0;
-#pragma unroll
-    for (int w = 0; w < kQBlock / 64; ++w) f |= nflag[slot][w];
-    return f != 0;
+    const int lane = threadIdx.x & 63;
+    const uint32_t f = lane < kQBlock / 64 ? nflag[slot][lane] : 0u;
+    return (bool)__any(f != 0u);
   };
   auto sdv = [&](long long m) {
     double r = (double)m * qc.inv_mbar;
