@@ -62,9 +62,14 @@ __device__ __forceinline__ void axis_span(float f, float rem, int lo, int hi, in
   b = min(hi, (int)ceilf(f + w));
 }
 
-// Integer units of one kernel value w (cells^-3 per unit particle mass).
+// Integer units of one kernel value w (cells^-3 per unit particle mass):
+// rint(w 2^40), ties to even.  w 2^40 is exact in FP64 and below 2^39
+// (w <= 8 / (pi h^3) < 1/2 for h >= 2); adding 2^52, where doubles are one
+// apart, rounds it and leaves the integer in the low mantissa bits.
 __device__ __forceinline__ unsigned long long spline_units(float w) {
-  return (unsigned long long)__double2ll_rn((double)w * 0x1p40);
+#pragma clang fp contract(off)
+  const double t = (double)w * 0x1p40;
+  return (unsigned long long)__double_as_longlong(t + 0x1p52) & 0x000FFFFFFFFFFFFFull;
 }
 
 template <int LOGN, bool FIXED>
@@ -222,9 +227,12 @@ __global__ void __launch_bounds__(kBlock) k_spline_qforce(const void* __restrict
           const float dz = (float)oz - fz;
           const float r2 = dxy2 + dz * dz;
           if (r2 > h2 || r2 == 0.0f) continue;
-          const float r = sqrtf(r2);
-          // Q_j dW/dr / r times the node offset x_j - q_i
-          const float g = qmesh[rxy + ((iz + oz) & MASK)] * spline_slope(r * inv_h) / r;
+          // Q_j dW/dr / r times the node offset x_j - q_i; 1/r from the
+          // hardware reciprocal square root, its argument held normal (below
+          // 2^-100 cell^2 the term, dW/dr / r times an offset under 2^-50,
+          // vanishes either way)
+          const float ri = __builtin_amdgcn_rsqf(fmaxf(r2, 0x1p-100f));
+          const float g = qmesh[rxy + ((iz + oz) & MASK)] * spline_slope(r2 * ri * inv_h) * ri;
           ax = fmaf(g, dx, ax);
           ay = fmaf(g, dy, ay);
           az = fmaf(g, dz, az);
