@@ -51,6 +51,12 @@ __device__ __forceinline__ float spline_slope(float q) {
   return -6.0f * t * t;
 }
 
+// r from r^2 through the hardware reciprocal square root (about 1 ulp; its
+// argument held normal, and r = 0 for r^2 = 0).
+__device__ __forceinline__ float spline_r(float r2) {
+  return r2 * __builtin_amdgcn_rsqf(fmaxf(r2, 0x1p-100f));
+}
+
 // Offsets o in [lo, hi] along one axis that may satisfy (o - f)^2 <= rem,
 // rem being h^2 less the other axes' squared distances: the integers in
 // [f - sqrt(rem), f + sqrt(rem)], widened to the enclosing integers so that
@@ -105,7 +111,7 @@ __global__ void __launch_bounds__(kBlock) k_spline_deposit(const void* __restric
           const float dz = (float)oz - fz;
           const float r2 = dxy2 + dz * dz;
           if (r2 > h2) continue;
-          const float q = sqrtf(r2) * inv_h;
+          const float q = spline_r(r2) * inv_h;
           atomicAdd(&mass[rxy + ((iz + oz) & MASK)], spline_units(coef * spline_shape(q)));
         }
       }
@@ -168,7 +174,7 @@ __global__ void __launch_bounds__(kSplineBlock) k_spline_deposit_tiled(
           const float dz = (float)c - fz;
           const float r2 = dxy2 + dz * dz;
           if (r2 > h2) continue;
-          const unsigned long long w = spline_units(coef * spline_shape(sqrtf(r2) * inv_h));
+          const unsigned long long w = spline_units(coef * spline_shape(spline_r(r2) * inv_h));
           if (inside)
             atomicAdd(&win[((rx + a - lo) * WY + (ry + b - lo)) * WZ + (rz + c - lo)], w);
           else
