@@ -59,11 +59,12 @@ __device__ __forceinline__ float spline_r(float r2) {
 
 // Offsets o in [lo, hi] along one axis that may satisfy (o - f)^2 <= rem,
 // rem being h^2 less the other axes' squared distances: the integers in
-// [f - sqrt(rem), f + sqrt(rem)], widened to the enclosing integers so that
-// rounding of the square root never drops a node; the exact test on r^2
-// inside the loops decides, so the nodes visited are those of the full cube.
+// [f - sqrt(rem), f + sqrt(rem)], widened to the enclosing integers, so that
+// any error of the square root below one cell never drops a node (the
+// hardware square root, about 1 ulp); the exact test on r^2 inside the loops
+// decides, so the nodes visited are those of the full cube.
 __device__ __forceinline__ void axis_span(float f, float rem, int lo, int hi, int& a, int& b) {
-  const float w = sqrtf(fmaxf(rem, 0.0f));
+  const float w = __builtin_amdgcn_sqrtf(fmaxf(rem, 0.0f));
   a = max(lo, (int)floorf(f - w));
   b = min(hi, (int)ceilf(f + w));
 }
