@@ -185,7 +185,9 @@ pm_status pm_force(pm_ctx* ctx, const float* d_phi, const float* d_q,
  * Comoving kick factors int da/(a^2 H) (gravity) and int da/(a^3 H) (Q,
  * drift) are computed on the host in FP64; half-kicks split at sqrt(a0 a1).
  * flags: PM_CONTINUE or 0.  On return the context's phi and Q are those of
- * the final positions. */
+ * the final positions.  PM_FIXED32 drifts are exact (the displacement in
+ * fixed-point units rounded to nearest, ties to even, wrapped modulo 2^32)
+ * for displacements below 2^51 units (2^19 box lengths) per step. */
 pm_status pm_step(pm_ctx* ctx, void* d_pos, float* d_vel, const double* times,
                   int32_t nsteps, int32_t flags);
 
