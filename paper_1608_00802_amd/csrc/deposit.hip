@@ -90,8 +90,12 @@ __global__ void __launch_bounds__(kBlock) k_deposit_f32(const float* __restrict_
 // atomic per non-zero cell.  Particles that left their tile since the sort
 // deposit with global atomics directly, so the result never depends on how
 // well sorted the particles are.
+// Threads per block of the tiled deposit: its 34 KB window leaves room for
+// four blocks per CU, so 512-thread blocks fill all 32 wave slots.
+constexpr int kDepBlock = 512;
+
 template <int LOGN, bool FIXED>
-__global__ void __launch_bounds__(kBlock) k_deposit_tiled(const void* __restrict__ pos,
+__global__ void __launch_bounds__(kDepBlock) k_deposit_tiled(const void* __restrict__ pos,
                                                           int64_t np, TileMap tm,
                                                           void* __restrict__ mass_v, Batch bt) {
   using T = typename std::conditional<FIXED, unsigned long long, float>::type;
@@ -111,9 +115,9 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiled(const void* __restrict
   unsigned lo, hi;
   if (!chunk_of(tm, t, lo, hi)) return;
   const int ox = (t / (NTY * NTZ)) * TX, oy = ((t / NTZ) % NTY) * TY, oz = (t % NTZ) * TZ;
-  for (int c = threadIdx.x; c < WX * WY * WZ; c += kBlock) acc[c] = (T)0;
+  for (int c = threadIdx.x; c < WX * WY * WZ; c += kDepBlock) acc[c] = (T)0;
   __syncthreads();
-  for (unsigned i = lo + threadIdx.x; i < hi; i += kBlock) {
+  for (unsigned i = lo + threadIdx.x; i < hi; i += kDepBlock) {
     int ix, iy, iz;
     T w[8];
     if constexpr (FIXED) {
@@ -133,7 +137,7 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiled(const void* __restrict
     }
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < WX * WY * WZ; c += kBlock) {
+  for (int c = threadIdx.x; c < WX * WY * WZ; c += kDepBlock) {
     const T v = acc[c];
     if (v != (T)0) {
       const int lx = c / (WY * WZ), ly = (c / WZ) % WY, lz = c % WZ;
@@ -167,7 +171,7 @@ hipError_t launch_deposit_fixed_tiled(const uint32_t* pos, int64_t np, int logn,
                                       hipStream_t s, const Batch& bt) {
   const dim3 g(tiled_grid(np, tm.tiles), bt.count);
 #define L_(LN) \
-  hipLaunchKernelGGL((k_deposit_tiled<LN, true>), g, dim3(kBlock), 0, s, pos, np, tm, mass, bt)
+  hipLaunchKernelGGL((k_deposit_tiled<LN, true>), g, dim3(kDepBlock), 0, s, pos, np, tm, mass, bt)
   FDM_LOGN_SWITCH(logn, L_)
 #undef L_
   return hipGetLastError();
@@ -177,7 +181,7 @@ hipError_t launch_deposit_f32_tiled(const float* pos, int64_t np, int logn, cons
                                     float* acc, hipStream_t s, const Batch& bt) {
   const dim3 g(tiled_grid(np, tm.tiles), bt.count);
 #define L_(LN) \
-  hipLaunchKernelGGL((k_deposit_tiled<LN, false>), g, dim3(kBlock), 0, s, pos, np, tm, acc, bt)
+  hipLaunchKernelGGL((k_deposit_tiled<LN, false>), g, dim3(kDepBlock), 0, s, pos, np, tm, acc, bt)
   FDM_LOGN_SWITCH(logn, L_)
 #undef L_
   return hipGetLastError();
